@@ -1,0 +1,214 @@
+/*
+ * etest.h -- C ABI of the MI355X (gfx950) permutation two-sample test library.
+ *
+ * The library evaluates the efficient permutation test of Chaibub Neto,
+ * "Computationally efficient permutation tests for the multivariate
+ * two-sample problem based on energy distance or maximum mean discrepancy
+ * statistics" (arXiv 2406.06488):
+ *
+ *   1. the three blocks D_XX, D_YY, D_XY (Euclidean distances, Alg. 3) or
+ *      K_XX, K_YY, K_XY (Gaussian kernel, remark after Alg. 3) are computed
+ *      once (Alg. 1, first three steps) -- never the pooled (nx+ny)^2 matrix
+ *      of the pre-computation strategy (Alg. 5), and never D_YX (the
+ *      memory-saving variant described after Alg. 1);
+ *   2. the observed statistic is eq. (1) (energy distance, ED) or eq. (2)
+ *      (biased MMD^2);
+ *   3. B resampled statistics are evaluated from those blocks only, one per
+ *      split of the pooled rows into x* (nx rows) and y* (ny rows) (Alg. 1
+ *      loop, Alg. 2);
+ *   4. the p-value is (1 + #{stat*_b >= threshold}) / (1 + B)
+ *      (Section 3.1, unbiased estimator of Phipson and Smyth).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - X is nx-by-p and Y is ny-by-p, row-major and contiguous, one sample per
+ *    row (Section 3, first paragraph).
+ *  - Split b (0 <= b < B) is drawn from (seed, b) alone: Philox4x32-10 with
+ *    key (seed mod 2^32, seed div 2^32) and counter (t div 2, b mod 2^32,
+ *    b div 2^32, 0) gives a 64-bit uniform u_t for pooled item t (X rows
+ *    first, then Y rows; even t takes words 0,1 and odd t words 2,3, low word
+ *    first); item t joins x* when floor(u_t * (n - t) / 2^64) < need, where
+ *    need starts at nx and drops by one at each member (selection sampling).
+ *    So a run can be split into b-ranges and resumed bit-exactly.
+ *  - The counting threshold is the identity split (x* = x, y* = y) evaluated
+ *    by the same code that evaluates the B resampled splits; it equals the
+ *    observed statistic up to rounding, and guarantees that a resampled split
+ *    equal to the observed one is counted.
+ *  - Gaussian kernel: k(x, y) = exp(-gamma * ||x - y||^2), gamma = 1/sigma^2.
+ *  - Every function returns an etest_status.  On error nothing is written to
+ *    the caller's outputs and etest_last_error() returns a message for the
+ *    calling thread.  No C++ exception crosses this boundary.
+ *  - Buffers are owned by the caller.  Host-buffer calls copy the inputs and
+ *    keep no pointer after they return.  Device-buffer calls require the
+ *    buffers to stay valid until the call returns (synchronous calls) or the
+ *    stream reaches the work (the *_async calls).
+ *  - There is no CPU fallback: every numerical step runs in the library's HIP
+ *    kernels on the current HIP device.
+ *  - Results depend only on (X, Y, p, B, seed, kind, prec, gamma), never on
+ *    what else is in the same batch or server.
+ */
+#ifndef ETEST_H
+#define ETEST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ETEST_OK = 0,
+  ETEST_EINVAL = 1,      /* nx < 1, ny < 1, p < 1, B < 0, NULL pointer, gamma <= 0 or
+                            non-finite, nx + ny > 2^31 - 1, bad request field        */
+  ETEST_ENONFINITE = 2,  /* X or Y holds a NaN or an Inf                                 */
+  ETEST_ENOMEM = 3,      /* device memory, or the server's memory budget, exhausted      */
+  ETEST_EDEVICE = 4,     /* a HIP runtime call failed                                    */
+  ETEST_EBUSY = 5,       /* server request not finished yet / server queue full         */
+  ETEST_ENOTFOUND = 6    /* unknown server request id                                    */
+} etest_status;
+
+typedef enum {
+  ETEST_PREC_F64 = 0,         /* FP64 inputs, FP64 blocks, FP64 reductions                */
+  ETEST_PREC_F32 = 1,         /* FP32 inputs, FP32 Gram on MFMA, FP32 blocks, FP64 sums   */
+  ETEST_PREC_BF16_REFINED = 2 /* FP32 inputs, BF16 Gram on MFMA with FP32 accumulation,   */
+                              /* pairs with d^2 < 1e-3 (|x|^2 + |y|^2) recomputed as a    */
+                              /* direct FP32 difference, FP64 sums                        */
+} etest_prec;
+
+typedef enum {
+  ETEST_ED = 0, /* energy distance, eq. (1)             */
+  ETEST_MMD = 1 /* biased MMD^2, Gaussian kernel, eq. (2) */
+} etest_kind;
+
+typedef struct {
+  double statistic; /* observed statistic, eq. (1) or (2), from FP64 block sums            */
+  double threshold; /* identity split as evaluated by the resampling stage                 */
+  double p_value;   /* (1 + count_ge) / (1 + B); 1 when B == 0                             */
+  int64_t count_ge; /* #{b : stat*_b >= threshold}                                         */
+  int64_t B;        /* number of resampled splits                                          */
+  int64_t n_refined;/* pairs recomputed by direct difference (BF16 form; 0 otherwise)      */
+} etest_result;
+
+/* One test described by device pointers (used by etest_run, etest_batch and the server). */
+typedef struct {
+  int32_t kind;       /* etest_kind                                                        */
+  int32_t prec;       /* etest_prec                                                        */
+  int64_t nx, ny, p;  /* sample sizes and dimension                                        */
+  int64_t B;          /* resampled splits, >= 0                                            */
+  uint64_t seed;      /* split stream seed                                                 */
+  double gamma;       /* MMD only: kernel exp(-gamma ||x-y||^2), gamma > 0                 */
+  const void* X;      /* nx*p row-major: double for ETEST_PREC_F64, float otherwise        */
+  const void* Y;      /* ny*p row-major, same type as X                                    */
+  double* perm_stats; /* [B] resampled statistics, or NULL to skip                        */
+} etest_request;
+
+/* ---- Synchronous calls on host buffers (the whole test: Alg. 1 end to end) ---- */
+
+/* Energy-distance permutation test on float32 host data.  prec is ETEST_PREC_F32 or
+   ETEST_PREC_BF16_REFINED.  perm_stats: host array of B doubles, or NULL.
+   out: host struct, required. */
+etest_status ed_test(const float* X, int64_t nx, const float* Y, int64_t ny, int64_t p,
+                     int64_t B, uint64_t seed, int32_t prec, double* perm_stats,
+                     etest_result* out);
+
+/* Gaussian-kernel MMD^2 permutation test on float32 host data (eq. 2). */
+etest_status mmd_test(const float* X, int64_t nx, const float* Y, int64_t ny, int64_t p,
+                      double gamma, int64_t B, uint64_t seed, int32_t prec,
+                      double* perm_stats, etest_result* out);
+
+/* Same as ed_test / mmd_test with float64 host data and ETEST_PREC_F64 throughout. */
+etest_status ed_test_f64(const double* X, int64_t nx, const double* Y, int64_t ny, int64_t p,
+                         int64_t B, uint64_t seed, double* perm_stats, etest_result* out);
+etest_status mmd_test_f64(const double* X, int64_t nx, const double* Y, int64_t ny,
+                          int64_t p, double gamma, int64_t B, uint64_t seed,
+                          double* perm_stats, etest_result* out);
+
+/* ---- Device buffers ---- */
+
+/* Run one test described by device pointers on `stream` (a hipStream_t, NULL = default
+   stream) and wait for it; fills the host struct `out`. */
+etest_status etest_run(const etest_request* req, void* stream, etest_result* out);
+
+/* Enqueue one test on `stream` and return without waiting.  d_out is a device pointer to
+   one etest_result, written when the stream reaches the end of the work.  Scratch memory
+   is taken from and returned to the stream-ordered allocator. */
+etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* stream);
+etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void* stream);
+
+/* n independent tests in one batched pass: every stage is one launch covering all tests,
+   and the launch sequence is captured once into a HIP graph and replayed.  outs: host
+   array of n results.  Each test's result equals what etest_run gives for it alone. */
+etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, etest_result* outs);
+
+/* ---- Stage-level calls (each step of the path, for parity checks) ---- */
+
+/* Splits b0 .. b0+count-1 as membership bits: words[(b - b0) * W + t/32] bit (t % 32) is 1
+   when pooled item t goes to x*; W = ceil((nx+ny)/32).  words: device, count*W uint32. */
+etest_status etest_membership(int64_t nx, int64_t ny, uint64_t seed, int64_t b0,
+                              int64_t count, uint32_t* words, void* stream);
+
+/* The three blocks of Alg. 1, written as full row-major matrices into device buffers:
+   dxx [nx*nx], dyy [ny*ny], dxy [nx*ny]; element type double for ETEST_PREC_F64 and
+   float otherwise.  Diagonals of dxx / dyy are exactly 0 (ED) or 1 (MMD). */
+etest_status etest_blocks(const etest_request* req, void* dxx, void* dyy, void* dxy,
+                          void* stream);
+
+/* Resampled statistics for caller-supplied splits: `words` (device, count*W uint32, same
+   layout as etest_membership) each hold exactly nx members; stats (device, count doubles).
+   Also returns the observed statistic and threshold in `out` (count_ge/p_value are over
+   these splits).  Lets a caller evaluate the identity, complement or an enumeration. */
+etest_status etest_perm_stats_from_membership(const etest_request* req, const uint32_t* words,
+                                              int64_t count, double* stats, void* stream,
+                                              etest_result* out);
+
+/* ---- Continuous-batching server ---- */
+
+typedef struct etest_server etest_server;
+
+typedef struct {
+  int64_t memory_budget_bytes; /* device bytes the server may hold for resident tests      */
+  int32_t max_resident;        /* slots: tests resident at once                            */
+  int32_t max_queue;           /* pending requests accepted before EBUSY                   */
+  int64_t chunk_updates;       /* resampling work per scheduler step (block entries x
+                                  splits summed over resident tests); <= 0 picks a default */
+} etest_server_config;
+
+/* Start a server with its own scheduler thread and HIP stream on the current device. */
+etest_status etest_server_create(const etest_server_config* cfg, etest_server** out);
+
+/* Queue a request.  X/Y/perm_stats are DEVICE pointers that must stay valid until the
+   request completes.  Returns ENOMEM if the request alone exceeds the memory budget,
+   EBUSY when the queue is full.  *id identifies the request. */
+etest_status etest_server_submit(etest_server* s, const etest_request* req, uint64_t* id);
+
+/* ETEST_OK and the result when finished (the id is then released), EBUSY while pending,
+   ENOTFOUND for an unknown id, or the request's own error status. */
+etest_status etest_server_poll(etest_server* s, uint64_t id, etest_result* out);
+
+/* Block until the request finishes; same results as poll. */
+etest_status etest_server_wait(etest_server* s, uint64_t id, etest_result* out);
+
+/* Queue depth, resident tests, device bytes held and completed count. */
+etest_status etest_server_stats(etest_server* s, int64_t* queued, int64_t* resident,
+                                int64_t* bytes_held, int64_t* completed);
+
+/* Finish outstanding work, join the scheduler thread and free everything. */
+etest_status etest_server_destroy(etest_server* s);
+
+/* ---- Diagnostics ---- */
+
+/* Message for the calling thread's last error ("" when none).  Owned by the library. */
+const char* etest_last_error(void);
+
+/* Device bytes a single test needs (inputs excluded); used for server admission.  Pure
+   host arithmetic: valid without a GPU. */
+etest_status etest_footprint(const etest_request* req, int64_t* bytes);
+
+/* Check a request's arguments without touching the device (same rules as every call). */
+etest_status etest_validate(const etest_request* req);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETEST_H */
