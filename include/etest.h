@@ -207,6 +207,16 @@ etest_status etest_footprint(const etest_request* req, int64_t* bytes);
 /* Check a request's arguments without touching the device (same rules as every call). */
 etest_status etest_validate(const etest_request* req);
 
+/* Stage timing of the calling thread's etest_run / ed_test / mmd_test calls: when on, HIP
+   events on the call's stream bracket each stage and their elapsed times accumulate.
+   Stages: 0 staging (column means, cast, norms), 1 blocks (Gram + epilogue), 2 split stream,
+   3 block sums + observed statistic, 4 centring, 5 resampling, 6 statistics + p-value.
+   etest_profile_enable(1) also resets the totals. */
+etest_status etest_profile_enable(int32_t on);
+
+/* Accumulated milliseconds and launch counts per stage (arrays of n <= 7 entries). */
+etest_status etest_profile_read(double* ms, int64_t* launches, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

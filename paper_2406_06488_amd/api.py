@@ -1,0 +1,233 @@
+"""Python front end of the C ABI.
+
+Host arrays (numpy) go through the host-buffer calls; torch tensors on the GPU
+go through the device-buffer calls on torch's current stream.  Every numerical
+step runs in the HIP library; this module only marshals arguments.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import ED, MMD, PREC_BF16_REFINED, PREC_F32, PREC_F64, Request, Result, check
+
+PRECS = {"f64": PREC_F64, "f32": PREC_F32, "bf16r": PREC_BF16_REFINED}
+KINDS = {"ed": ED, "mmd": MMD}
+
+
+def _prec(p):
+    return PRECS[p] if isinstance(p, str) else int(p)
+
+
+def _kind(k):
+    return KINDS[k] if isinstance(k, str) else int(k)
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def ed_test(X, Y, B, seed, prec="f32", with_perm_stats=True):
+    """Energy-distance permutation test on host arrays (float32, or float64 for prec='f64')."""
+    L = _lib.load()
+    pr = _prec(prec)
+    dt = np.float64 if pr == PREC_F64 else np.float32
+    X = np.ascontiguousarray(X, dtype=dt)
+    Y = np.ascontiguousarray(Y, dtype=dt)
+    ps = np.zeros(max(B, 1)) if with_perm_stats else None
+    r = Result()
+    pp = _ptr(ps) if ps is not None else None
+    if pr == PREC_F64:
+        check(L.ed_test_f64(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], X.shape[1], B, seed, pp,
+                            ctypes.byref(r)))
+    else:
+        check(L.ed_test(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], X.shape[1], B, seed, pr, pp,
+                        ctypes.byref(r)))
+    out = r.as_dict()
+    out["perm_stats"] = ps[:B].copy() if ps is not None else None
+    return out
+
+
+def mmd_test(X, Y, gamma, B, seed, prec="f32", with_perm_stats=True):
+    """Gaussian-kernel MMD^2 permutation test on host arrays."""
+    L = _lib.load()
+    pr = _prec(prec)
+    dt = np.float64 if pr == PREC_F64 else np.float32
+    X = np.ascontiguousarray(X, dtype=dt)
+    Y = np.ascontiguousarray(Y, dtype=dt)
+    ps = np.zeros(max(B, 1)) if with_perm_stats else None
+    r = Result()
+    pp = _ptr(ps) if ps is not None else None
+    if pr == PREC_F64:
+        check(L.mmd_test_f64(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], X.shape[1], gamma, B, seed,
+                             pp, ctypes.byref(r)))
+    else:
+        check(L.mmd_test(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], X.shape[1], gamma, B, seed, pr,
+                         pp, ctypes.byref(r)))
+    out = r.as_dict()
+    out["perm_stats"] = ps[:B].copy() if ps is not None else None
+    return out
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_request(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stats=None):
+    """Request over device tensors X (nx x p), Y (ny x p); perm_stats a float64 device tensor or None."""
+    r = Request()
+    r.kind = _kind(kind)
+    r.prec = _prec(prec)
+    r.nx, r.p = X.shape
+    r.ny = Y.shape[0]
+    r.B = B
+    r.seed = seed
+    r.gamma = gamma
+    r.X = X.data_ptr()
+    r.Y = Y.data_ptr()
+    r.perm_stats = perm_stats.data_ptr() if perm_stats is not None else None
+    return r
+
+
+def _check_dev(X, Y, prec):
+    import torch
+    want = torch.float64 if _prec(prec) == PREC_F64 else torch.float32
+    for T in (X, Y):
+        if not T.is_cuda or T.dtype != want or not T.is_contiguous() or T.dim() != 2:
+            raise ValueError("device inputs must be contiguous 2-D %s CUDA tensors" % want)
+
+
+def run(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True):
+    """One test on device tensors (torch), synchronous.  Returns a dict; perm_stats stays on device."""
+    import torch
+    _check_dev(X, Y, prec)
+    ps = torch.empty(max(B, 1), dtype=torch.float64, device=X.device) if with_perm_stats else None
+    req = make_request(X, Y, B, seed, kind, prec, gamma, ps)
+    r = Result()
+    check(_lib.load().etest_run(ctypes.byref(req), _stream(), ctypes.byref(r)))
+    out = r.as_dict()
+    out["perm_stats"] = ps[:B] if ps is not None else None
+    return out
+
+
+def run_async(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stats=None):
+    """Enqueue one test on torch's current stream; returns a device buffer holding the
+    etest_result (6 x 8 bytes).  Use result_from_device() after synchronising."""
+    import torch
+    _check_dev(X, Y, prec)
+    out = torch.zeros(6, dtype=torch.float64, device=X.device)
+    req = make_request(X, Y, B, seed, kind, prec, gamma, perm_stats)
+    fn = _lib.load().ed_test_async if _kind(kind) == ED else _lib.load().mmd_test_async
+    check(fn(ctypes.byref(req), ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def result_from_device(buf):
+    raw = buf.cpu().numpy().tobytes()
+    r = Result.from_buffer_copy(raw)
+    return r.as_dict()
+
+
+def batch(requests, keep=None):
+    """Many tests in one batched, graph-captured pass.  requests: list of Request."""
+    n = len(requests)
+    arr = (Request * n)(*requests)
+    outs = (Result * n)()
+    check(_lib.load().etest_batch(arr, n, _stream(), outs))
+    return [o.as_dict() for o in outs]
+
+
+def membership(nx, ny, seed, b0, count, device="cuda"):
+    """Splits b0..b0+count-1 as packed bits (count x ceil(n/32) int32 device tensor)."""
+    import torch
+    W = (nx + ny + 31) // 32
+    words = torch.zeros((count, W), dtype=torch.int32, device=device)
+    check(_lib.load().etest_membership(nx, ny, seed, b0, count, ctypes.c_void_p(words.data_ptr()),
+                                       _stream()))
+    return words
+
+
+def unpack_words(words, n):
+    """Packed membership words -> 0/1 uint8 array (count x n) on the host."""
+    w = words.cpu().numpy().astype(np.uint32)
+    bits = (w[:, :, None] >> np.arange(32, dtype=np.uint32)[None, None, :]) & 1
+    return bits.reshape(w.shape[0], -1)[:, :n].astype(np.uint8)
+
+
+def pack_splits(Z):
+    """0/1 array (count x n) -> packed words (count x ceil(n/32)) as int32 numpy."""
+    Z = np.asarray(Z, dtype=np.uint64)
+    c, n = Z.shape
+    W = (n + 31) // 32
+    pad = np.zeros((c, W * 32), dtype=np.uint64)
+    pad[:, :n] = Z
+    pad = pad.reshape(c, W, 32)
+    words = (pad << np.arange(32, dtype=np.uint64)[None, None, :]).sum(axis=2)
+    return words.astype(np.uint32).view(np.int32)
+
+
+def blocks(X, Y, kind="ed", prec="f32", gamma=0.0):
+    """The three blocks (D_XX, D_YY, D_XY) as device tensors."""
+    import torch
+    _check_dev(X, Y, prec)
+    dt = torch.float64 if _prec(prec) == PREC_F64 else torch.float32
+    nx, ny = X.shape[0], Y.shape[0]
+    dxx = torch.empty((nx, nx), dtype=dt, device=X.device)
+    dyy = torch.empty((ny, ny), dtype=dt, device=X.device)
+    dxy = torch.empty((nx, ny), dtype=dt, device=X.device)
+    req = make_request(X, Y, 0, 0, kind, prec, gamma)
+    check(_lib.load().etest_blocks(ctypes.byref(req), ctypes.c_void_p(dxx.data_ptr()),
+                                   ctypes.c_void_p(dyy.data_ptr()),
+                                   ctypes.c_void_p(dxy.data_ptr()), _stream()))
+    return dxx, dyy, dxy
+
+
+def perm_stats_from_membership(X, Y, words, kind="ed", prec="f32", gamma=0.0):
+    """Statistics for caller-supplied splits (packed words, count x ceil(n/32), device int32)."""
+    import torch
+    _check_dev(X, Y, prec)
+    count = words.shape[0]
+    stats = torch.empty(count, dtype=torch.float64, device=X.device)
+    req = make_request(X, Y, count, 0, kind, prec, gamma)
+    r = Result()
+    check(_lib.load().etest_perm_stats_from_membership(
+        ctypes.byref(req), ctypes.c_void_p(words.data_ptr()), count,
+        ctypes.c_void_p(stats.data_ptr()), _stream(), ctypes.byref(r)))
+    out = r.as_dict()
+    out["perm_stats"] = stats
+    return out
+
+
+def validate(nx, ny, p, B, kind="ed", prec="f32", gamma=1.0, X=1, Y=1):
+    """Argument check without a device (returns the status code)."""
+    r = Request()
+    r.kind, r.prec, r.nx, r.ny, r.p, r.B, r.seed, r.gamma = (_kind(kind), _prec(prec), nx, ny, p,
+                                                             B, 0, gamma)
+    r.X, r.Y, r.perm_stats = X, Y, None
+    return _lib.load().etest_validate(ctypes.byref(r))
+
+
+def footprint(nx, ny, p, B, kind="ed", prec="f32"):
+    r = Request()
+    r.kind, r.prec, r.nx, r.ny, r.p, r.B, r.gamma = _kind(kind), _prec(prec), nx, ny, p, B, 1.0
+    out = ctypes.c_int64()
+    check(_lib.load().etest_footprint(ctypes.byref(r), ctypes.byref(out)))
+    return out.value
+
+
+def last_error():
+    return _lib.load().etest_last_error().decode()
+
+
+def profile_enable(on=True):
+    check(_lib.load().etest_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """{stage name: (total ms, launches)} for this thread's synchronous calls since enable."""
+    n = len(_lib.STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    check(_lib.load().etest_profile_read(ms, cnt, n))
+    return {name: (ms[k], cnt[k]) for k, name in enumerate(_lib.STAGES)}

@@ -1,0 +1,130 @@
+// Shared definitions of the gfx950 kernels and the host runtime.
+//
+// Data layout in HBM for one test (n_pad = (tx + ty) * TILE):
+//   W      [n_pad][p_pad]   staged operand rows: X rows, zero rows up to a TILE
+//                           boundary, Y rows, zero rows (column-mean centred for
+//                           the FP32/BF16 forms; FP64/FP32/BF16 elements)
+//   nrm    [n_pad]          squared row norms of the staged rows
+//   D      [ntiles][T][T]   upper tiles (i <= j) of the pooled tile grid: XX upper
+//                           tiles, every XY tile, YY upper tiles -- never a YX tile
+//   tsum   [ntiles][2][T]   FP64 row / column sums of each stored tile
+//   rsum   [n_pad][2]       pooled row sums: same-sample part, cross-sample part
+//   planes [ntiles][S][T*T] double-centred tiles split into S bf16 planes in MFMA
+//                           A-fragment order (FP64 form: one FP64 row-major tile)
+//   Z      [n_pad/32][B_pad] split membership bits, word w of column c holds items
+//                           32w..32w+31; columns 0..B-1 drawn splits, column B the
+//                           identity split, the rest zero
+//   part   [n_rowk][B_pad]  FP64 partial quadratic forms per (row tile, column range)
+//   pstat  [B_pad]          resampled statistics
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace et {
+
+constexpr int TILE = 128;            // edge of a stored block tile
+constexpr int TILE_WORDS = TILE / 32;
+constexpr int NP = 256;              // split columns per resampling workgroup
+
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
+enum { KIND_ED = 0, KIND_MMD = 1 };
+
+// Result written by the device (the public etest_result plus a status word).
+struct DevResult {
+  double statistic, threshold, p_value;
+  int64_t count_ge, B, n_refined;
+  int32_t status, pad;
+};
+
+struct TestDesc {
+  int32_t kind, prec, splits, refine;
+  int32_t nx, ny, p, p_pad;
+  int32_t tx, ty, nt, ntiles;
+  int32_t kc, n_rowk, nrowchunks, pad0;
+  int64_t B, B_pad;
+  uint64_t seed;
+  double gamma;
+  const void* X;
+  const void* Y;
+  double* colpart;
+  double* colmean;
+  void* W;
+  void* nrm;
+  void* D;
+  double* tsum;
+  double* rsum;
+  double* obs;       // [0..2] S_XX, S_YY, S_XY; [3] observed statistic; [4] R
+  void* planes;
+  uint32_t* Z;
+  double* part;
+  double* pstat;
+  int32_t* flags;    // [0] non-finite input seen, [1] refined pair count
+  double* perm_out;
+  DevResult* result;
+};
+
+// Which test a flattened workgroup index belongs to: offs[t] <= bid < offs[t+1].
+__device__ inline int find_test(const int64_t* __restrict__ offs, int ntests, int64_t bid) {
+  int lo = 0, hi = ntests - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Stored upper tile index of (i, j), i <= j, in an nt x nt tile grid.
+__host__ __device__ inline int tile_index(int i, int j, int nt) {
+  return i * nt - (i * (i - 1)) / 2 + (j - i);
+}
+
+// Inverse of tile_index.
+__device__ inline void tile_coords(int t, int nt, int* pi, int* pj) {
+  int i = 0;
+  int start = 0;
+  while (true) {
+    int len = nt - i;
+    if (t < start + len) break;
+    start += len;
+    ++i;
+  }
+  *pi = i;
+  *pj = i + (t - start);
+}
+
+// Real rows in pooled tile i (rest is padding).
+__device__ inline int tile_rows(const TestDesc& d, int i) {
+  if (i < d.tx) {
+    int r = d.nx - i * TILE;
+    return r < TILE ? r : TILE;
+  }
+  int r = d.ny - (i - d.tx) * TILE;
+  return r < TILE ? r : TILE;
+}
+
+// Row-range unit u -> (row tile i, first column tile j0, end j1).
+__device__ inline void rowk_coords(const TestDesc& d, int u, int* pi, int* pj0, int* pj1) {
+  int i = 0, start = 0;
+  while (true) {
+    int len = (d.nt - i + d.kc - 1) / d.kc;
+    if (u < start + len) break;
+    start += len;
+    ++i;
+  }
+  int c = u - start;
+  *pi = i;
+  *pj0 = i + c * d.kc;
+  int e = *pj0 + d.kc;
+  *pj1 = e < d.nt ? e : d.nt;
+}
+
+// Round-to-nearest-even float -> bf16 bits (finite inputs).
+__device__ inline uint16_t f32_to_bf16_rn(float f) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t r = 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)((u + r) >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+}  // namespace et

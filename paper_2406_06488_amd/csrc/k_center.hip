@@ -1,0 +1,105 @@
+// Double centring of the stored tiles.
+//
+// Adding f(a) + f(b) to every pooled pair leaves every resampled ED / MMD
+// statistic unchanged: each pooled row of eq. (1)'s weights sums to zero
+// (-nx/nx^2 + ny/(nx ny) = 0).  With f(a) = -r_a/n + R/(2 n^2), r_a the pooled
+// row sum and R their total, the centred matrix has zero row sums, so for a
+// split z (1 = member of x*)
+//     ED*(z)  = -(1/nx + 1/ny)^2 * z^T Dc z,
+//     MMD*(z) = +(1/nx + 1/ny)^2 * z^T Kc z,
+// a single quadratic form over the three stored blocks.  Diagonal tiles are
+// halved, so that z^T Dc z = 2 * sum over stored tiles (i <= j) of z_i^T T_ij z_j.
+//
+// FP32/BF16 forms: the centred value, rounded to FP32, is split into S bf16
+// planes hi + mid + lo (S = 3 represents the FP32 value exactly) laid out in
+// v_mfma_f32_32x32x16_bf16 A-fragment order: fragment (mb, ks) of a tile is 64
+// lanes x 8 bf16, lane = row%32 + 32 * ((col%16)/8), for rows 32 mb.. and
+// columns 16 ks.. .  FP64 form: one FP64 row-major tile.
+#include "common.h"
+
+namespace et {
+
+__device__ inline double center_value(const TestDesc& d, int i, int j, int r, int col, int rows_i,
+                                      int rows_j, double v, double inv_n, double c0) {
+  if (r >= rows_i || col >= rows_j) return 0.0;
+  const int64_t pa = (int64_t)i * TILE + r, pb = (int64_t)j * TILE + col;
+  const double ca = (d.rsum[pa * 2] + d.rsum[pa * 2 + 1]) * inv_n;
+  const double cb = (d.rsum[pb * 2] + d.rsum[pb * 2 + 1]) * inv_n;
+  double x = ((v - ca) - cb) + c0;
+  if (i == j) x *= 0.5;
+  return x;
+}
+
+__global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict__ descs,
+                                                      const int64_t* __restrict__ offs,
+                                                      int ntests) {
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc& d = descs[ti];
+  const int t = (int)(blockIdx.x - offs[ti]);
+  int i, j;
+  tile_coords(t, d.nt, &i, &j);
+  const int rows_i = tile_rows(d, i), rows_j = tile_rows(d, j);
+  const double n = (double)d.nx + (double)d.ny;
+  const double inv_n = 1.0 / n;
+  const double c0 = d.obs[4] / (n * n);
+  const int S = d.splits;
+  const float* Dt = (const float*)d.D + (int64_t)t * TILE * TILE;
+  uint16_t* P = (uint16_t*)d.planes + (int64_t)t * S * TILE * TILE;
+  for (int q = threadIdx.x; q < TILE * TILE / 8; q += 256) {
+    const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
+    const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
+    uint16_t hi[8], mid[8], lo[8];
+    for (int e = 0; e < 8; ++e) {
+      const double x = center_value(d, i, j, r, c0l + e, rows_i, rows_j,
+                                    (double)Dt[r * TILE + c0l + e], inv_n, c0);
+      const float v = (float)x;
+      hi[e] = f32_to_bf16_rn(v);
+      const float r1 = v - bf16_to_f32(hi[e]);
+      mid[e] = f32_to_bf16_rn(r1);
+      const float r2 = r1 - bf16_to_f32(mid[e]);
+      lo[e] = f32_to_bf16_rn(r2);
+    }
+    uint4 w;
+    w.x = hi[0] | ((uint32_t)hi[1] << 16); w.y = hi[2] | ((uint32_t)hi[3] << 16);
+    w.z = hi[4] | ((uint32_t)hi[5] << 16); w.w = hi[6] | ((uint32_t)hi[7] << 16);
+    *(uint4*)(P + (int64_t)q * 8) = w;
+    if (S > 1) {
+      w.x = mid[0] | ((uint32_t)mid[1] << 16); w.y = mid[2] | ((uint32_t)mid[3] << 16);
+      w.z = mid[4] | ((uint32_t)mid[5] << 16); w.w = mid[6] | ((uint32_t)mid[7] << 16);
+      *(uint4*)(P + TILE * TILE + (int64_t)q * 8) = w;
+    }
+    if (S > 2) {
+      w.x = lo[0] | ((uint32_t)lo[1] << 16); w.y = lo[2] | ((uint32_t)lo[3] << 16);
+      w.z = lo[4] | ((uint32_t)lo[5] << 16); w.w = lo[6] | ((uint32_t)lo[7] << 16);
+      *(uint4*)(P + 2 * TILE * TILE + (int64_t)q * 8) = w;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_center_f64(const TestDesc* __restrict__ descs,
+                                                    const int64_t* __restrict__ offs, int ntests) {
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc& d = descs[ti];
+  const int t = (int)(blockIdx.x - offs[ti]);
+  int i, j;
+  tile_coords(t, d.nt, &i, &j);
+  const int rows_i = tile_rows(d, i), rows_j = tile_rows(d, j);
+  const double n = (double)d.nx + (double)d.ny;
+  const double inv_n = 1.0 / n;
+  const double c0 = d.obs[4] / (n * n);
+  const double* Dt = (const double*)d.D + (int64_t)t * TILE * TILE;
+  double* P = (double*)d.planes + (int64_t)t * TILE * TILE;
+  for (int e = threadIdx.x; e < TILE * TILE; e += 256) {
+    const int r = e / TILE, col = e % TILE;
+    P[e] = center_value(d, i, j, r, col, rows_i, rows_j, Dt[e], inv_n, c0);
+  }
+}
+
+void launch_center(bool f64, int64_t blocks, hipStream_t st, const TestDesc* d,
+                   const int64_t* offs, int n) {
+  if (blocks <= 0) return;
+  if (f64) hipLaunchKernelGGL(k_center_f64, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+  else hipLaunchKernelGGL(k_center_split, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+}
+
+}  // namespace et

@@ -1,0 +1,284 @@
+// Block stage: every stored tile (i <= j) of the pooled tile grid is one
+// workgroup.  FP32 / BF16 forms: Gram tile G = W_i W_j^T on MFMA, epilogue
+// d^2 = |w_a|^2 + |w_b|^2 - 2 g (clamped at 0), then D = sqrt(d^2) (energy
+// distance, Alg. 3) or K = exp(-gamma d^2) (Gaussian kernel).  The BF16 form
+// recomputes pairs with d^2 < 1e-3 (|w_a|^2 + |w_b|^2) as a direct FP32
+// difference of the input rows.  The FP64 form evaluates Alg. 3 as written
+// (sum of squared differences) on the vector ALU.
+//
+// Every stored tile also yields FP64 row sums and column sums, from which the
+// observed statistic (eq. 1 / eq. 2) and the double-centring constants follow.
+#include "common.h"
+
+namespace et {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int LDS_ROW_F32 = 36;   // 32 staged k + 4 pad (floats)
+constexpr int LDS_ROW_BF16 = 72;  // 64 staged k + 8 pad (bf16)
+constexpr int TILE_LDS = TILE + 1;
+
+struct TileCtx {
+  int t, i, j;
+  int rows_i, rows_j;
+  bool diag;
+};
+
+__device__ inline TileCtx tile_ctx(const TestDesc& d, int64_t local) {
+  TileCtx c;
+  c.t = (int)local;
+  tile_coords(c.t, d.nt, &c.i, &c.j);
+  c.rows_i = tile_rows(d, c.i);
+  c.rows_j = tile_rows(d, c.j);
+  c.diag = c.i == c.j;
+  return c;
+}
+
+// Input row (pooled, unpadded) of tile row r of pooled tile i.
+__device__ inline const float* input_row_f32(const TestDesc& d, int i, int r) {
+  if (i < d.tx) return (const float*)d.X + ((int64_t)i * TILE + r) * d.p;
+  return (const float*)d.Y + ((int64_t)(i - d.tx) * TILE + r) * d.p;
+}
+
+// d^2 -> stored block value; padding rows/columns hold 0.
+__device__ inline float block_value_f32(const TestDesc& d, const TileCtx& c, int r, int col,
+                                        float d2) {
+  if (r >= c.rows_i || col >= c.rows_j) return 0.0f;
+  if (c.diag && r == col) return d.kind == KIND_ED ? 0.0f : 1.0f;
+  d2 = fmaxf(d2, 0.0f);
+  return d.kind == KIND_ED ? sqrtf(d2) : expf((float)(-d.gamma) * d2);
+}
+
+// Row / column sums of the LDS tile and its coalesced store.
+__device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, float* tl) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  if (tid < TILE) {
+    for (int k = 0; k < TILE; ++k) s += (double)tl[tid * TILE_LDS + k];
+    d.tsum[(int64_t)c.t * 2 * TILE + tid] = s;
+  } else {
+    const int col = tid - TILE;
+    for (int k = 0; k < TILE; ++k) s += (double)tl[k * TILE_LDS + col];
+    d.tsum[(int64_t)c.t * 2 * TILE + TILE + col] = s;
+  }
+  float* D = (float*)d.D + (int64_t)c.t * TILE * TILE;
+  for (int e = tid; e < TILE * TILE; e += 256) D[e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
+}
+
+// ---------------------------------------------------------------- FP32 MFMA
+// 4 waves as 2 x 2, each 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x2_f32.
+__global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ descs,
+                                                  const int64_t* __restrict__ offs, int ntests) {
+  __shared__ float smem[TILE * TILE_LDS];
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc& d = descs[ti];
+  const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
+  const float* Wa = (const float*)d.W + (int64_t)c.i * TILE * d.p_pad;
+  const float* Wb = (const float*)d.W + (int64_t)c.j * TILE * d.p_pad;
+  float* As = smem;
+  float* Bs = smem + TILE * LDS_ROW_F32;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int wm = w >> 1, wn = w & 1, h = lane >> 5, lr = lane & 31;
+  f32x16 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
+
+  for (int k0 = 0; k0 < d.p_pad; k0 += 32) {
+    __syncthreads();
+    for (int s = 0; s < 4; ++s) {
+      const int q = tid + 256 * s;  // 1024 float4 per operand
+      const int row = q >> 3, c4 = (q & 7) * 4;
+      const float4 va = *(const float4*)(Wa + (int64_t)row * d.p_pad + k0 + c4);
+      const float4 vb = *(const float4*)(Wb + (int64_t)row * d.p_pad + k0 + c4);
+      *(float4*)(As + row * LDS_ROW_F32 + c4) = va;
+      *(float4*)(Bs + row * LDS_ROW_F32 + c4) = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      // lane half h supplies staged columns 16h .. 16h+15 (the same for A and B)
+      float4 av[2], bv[2];
+      for (int mb = 0; mb < 2; ++mb)
+        av[mb] = *(const float4*)(As + (wm * 64 + mb * 32 + lr) * LDS_ROW_F32 + 16 * h + 4 * s4);
+      for (int nb = 0; nb < 2; ++nb)
+        bv[nb] = *(const float4*)(Bs + (wn * 64 + nb * 32 + lr) * LDS_ROW_F32 + 16 * h + 4 * s4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        for (int mb = 0; mb < 2; ++mb)
+          for (int nb = 0; nb < 2; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][e], bv[nb][e], acc[mb][nb],
+                                                               0, 0, 0);
+    }
+  }
+  __syncthreads();
+  const float* nrm = (const float*)d.nrm;
+  for (int mb = 0; mb < 2; ++mb)
+    for (int nb = 0; nb < 2; ++nb) {
+      const int col = wn * 64 + nb * 32 + lr;
+      const float nc = nrm[(int64_t)c.j * TILE + col];
+      for (int e = 0; e < 16; ++e) {
+        const int r = wm * 64 + mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+        const float nr = nrm[(int64_t)c.i * TILE + r];
+        const float d2 = nr + nc - 2.0f * acc[mb][nb][e];
+        smem[r * TILE_LDS + col] = block_value_f32(d, c, r, col, d2);
+      }
+    }
+  finish_tile_f32(d, c, smem);
+}
+
+// ---------------------------------------------------------------- BF16 MFMA
+// Same arrangement with v_mfma_f32_32x32x16_bf16; pairs whose Gram-based d^2
+// falls below 1e-3 of the norm sum are recomputed from the FP32 input rows.
+__global__ void __launch_bounds__(256) k_gram_bf16(const TestDesc* __restrict__ descs,
+                                                   const int64_t* __restrict__ offs, int ntests) {
+  __shared__ float smem[TILE * TILE_LDS];
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc& d = descs[ti];
+  const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
+  const uint16_t* Wa = (const uint16_t*)d.W + (int64_t)c.i * TILE * d.p_pad;
+  const uint16_t* Wb = (const uint16_t*)d.W + (int64_t)c.j * TILE * d.p_pad;
+  uint16_t* As = (uint16_t*)smem;
+  uint16_t* Bs = As + TILE * LDS_ROW_BF16;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int wm = w >> 1, wn = w & 1, h = lane >> 5, lr = lane & 31;
+  f32x16 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
+
+  for (int k0 = 0; k0 < d.p_pad; k0 += 64) {
+    __syncthreads();
+    for (int s = 0; s < 4; ++s) {
+      const int q = tid + 256 * s;  // 1024 chunks of 8 bf16 per operand
+      const int row = q >> 3, c8 = (q & 7) * 8;
+      const uint4 va = *(const uint4*)(Wa + (int64_t)row * d.p_pad + k0 + c8);
+      const uint4 vb = *(const uint4*)(Wb + (int64_t)row * d.p_pad + k0 + c8);
+      *(uint4*)(As + row * LDS_ROW_BF16 + c8) = va;
+      *(uint4*)(Bs + row * LDS_ROW_BF16 + c8) = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      bf16x8 av[2], bv[2];
+      for (int mb = 0; mb < 2; ++mb)
+        av[mb] = *(const bf16x8*)(As + (wm * 64 + mb * 32 + lr) * LDS_ROW_BF16 + 16 * s + 8 * h);
+      for (int nb = 0; nb < 2; ++nb)
+        bv[nb] = *(const bf16x8*)(Bs + (wn * 64 + nb * 32 + lr) * LDS_ROW_BF16 + 16 * s + 8 * h);
+      for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb] =
+              __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  const float* nrm = (const float*)d.nrm;
+  int refined = 0;
+  for (int mb = 0; mb < 2; ++mb)
+    for (int nb = 0; nb < 2; ++nb) {
+      const int col = wn * 64 + nb * 32 + lr;
+      const float nc = nrm[(int64_t)c.j * TILE + col];
+      for (int e = 0; e < 16; ++e) {
+        const int r = wm * 64 + mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+        const float nr = nrm[(int64_t)c.i * TILE + r];
+        float d2 = nr + nc - 2.0f * acc[mb][nb][e];
+        if (d.refine && r < c.rows_i && col < c.rows_j && !(c.diag && r == col) &&
+            d2 < 1e-3f * (nr + nc)) {
+          const float* xa = input_row_f32(d, c.i, r);
+          const float* xb = input_row_f32(d, c.j, col);
+          float s = 0.0f;
+          for (int k = 0; k < d.p; ++k) {
+            const float df = xa[k] - xb[k];
+            s = fmaf(df, df, s);
+          }
+          d2 = s;
+          ++refined;
+        }
+        smem[r * TILE_LDS + col] = block_value_f32(d, c, r, col, d2);
+      }
+    }
+  if (refined) atomicAdd(&d.flags[1], refined);
+  finish_tile_f32(d, c, smem);
+}
+
+// ---------------------------------------------------------------- FP64 direct
+// Alg. 3 literally: sum over k of (x_ak - y_bk)^2 on the FP64 vector ALU.
+// Thread (tr, tc) owns rows tr + 16 a and columns tc + 16 b (a, b < 8).
+constexpr int KC64 = 16;
+__global__ void __launch_bounds__(256) k_dist_f64(const TestDesc* __restrict__ descs,
+                                                  const int64_t* __restrict__ offs, int ntests) {
+  __shared__ double As[TILE * (KC64 + 1)];
+  __shared__ double Bs[TILE * (KC64 + 1)];
+  __shared__ double rp[TILE * 16];
+  __shared__ double cp[16 * TILE];
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc& d = descs[ti];
+  const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
+  const double* Wa = (const double*)d.W + (int64_t)c.i * TILE * d.p_pad;
+  const double* Wb = (const double*)d.W + (int64_t)c.j * TILE * d.p_pad;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  double acc[8][8];
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+  for (int k0 = 0; k0 < d.p_pad; k0 += KC64) {
+    __syncthreads();
+    for (int e = tid; e < TILE * KC64; e += 256) {
+      const int row = e / KC64, k = e % KC64;
+      As[row * (KC64 + 1) + k] = Wa[(int64_t)row * d.p_pad + k0 + k];
+      Bs[row * (KC64 + 1) + k] = Wb[(int64_t)row * d.p_pad + k0 + k];
+    }
+    __syncthreads();
+    for (int k = 0; k < KC64; ++k) {
+      double av[8], bv[8];
+      for (int a = 0; a < 8; ++a) av[a] = As[(tr + 16 * a) * (KC64 + 1) + k];
+      for (int b = 0; b < 8; ++b) bv[b] = Bs[(tc + 16 * b) * (KC64 + 1) + k];
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+          const double df = av[a] - bv[b];
+          acc[a][b] = fma(df, df, acc[a][b]);
+        }
+    }
+  }
+  double* D = (double*)d.D + (int64_t)c.t * TILE * TILE;
+  double rs[8], cs[8];
+  for (int a = 0; a < 8; ++a) rs[a] = 0.0;
+  for (int b = 0; b < 8; ++b) cs[b] = 0.0;
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      const int r = tr + 16 * a, col = tc + 16 * b;
+      double v;
+      if (r >= c.rows_i || col >= c.rows_j) v = 0.0;
+      else if (c.diag && r == col) v = d.kind == KIND_ED ? 0.0 : 1.0;
+      else v = d.kind == KIND_ED ? sqrt(acc[a][b]) : exp(-d.gamma * acc[a][b]);
+      D[r * TILE + col] = v;
+      rs[a] += v;
+      cs[b] += v;
+    }
+  for (int a = 0; a < 8; ++a) rp[(tr + 16 * a) * 16 + tc] = rs[a];
+  for (int b = 0; b < 8; ++b) cp[tr * TILE + tc + 16 * b] = cs[b];
+  __syncthreads();
+  double s = 0.0;
+  if (tid < TILE) {
+    for (int q = 0; q < 16; ++q) s += rp[tid * 16 + q];
+    d.tsum[(int64_t)c.t * 2 * TILE + tid] = s;
+  } else {
+    const int col = tid - TILE;
+    for (int q = 0; q < 16; ++q) s += cp[q * TILE + col];
+    d.tsum[(int64_t)c.t * 2 * TILE + TILE + col] = s;
+  }
+}
+
+void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d,
+                 const int64_t* offs, int n) {
+  if (blocks <= 0) return;
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+  else if (prec == PREC_F32)
+    hipLaunchKernelGGL(k_gram_f32, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+  else
+    hipLaunchKernelGGL(k_gram_bf16, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+}
+
+}  // namespace et

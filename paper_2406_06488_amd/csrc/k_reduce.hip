@@ -1,0 +1,96 @@
+// Pooled row sums and the observed statistic.
+//
+// For pooled position a in row tile i, the same-sample part of its row sum
+// gathers row sums of tiles (i, j >= i) and column sums of tiles (j < i, i)
+// inside its own block (XX or YY); the cross-sample part gathers the XY tiles
+// (row sums for an X position, column sums for a Y position).  Summing the
+// parts over positions gives S_XX, S_YY and S_XY, the three block sums of
+// eq. (1) / eq. (2), accumulated with Neumaier compensation in FP64.
+#include "common.h"
+
+namespace et {
+
+__global__ void __launch_bounds__(256) k_rowsum(const TestDesc* __restrict__ descs,
+                                                const int64_t* __restrict__ offs, int ntests) {
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc& d = descs[ti];
+  const int64_t pos = (blockIdx.x - offs[ti]) * 256 + threadIdx.x;
+  const int64_t npad = (int64_t)d.nt * TILE;
+  if (pos >= npad) return;
+  const int i = (int)(pos / TILE), r = (int)(pos % TILE);
+  const double* ts = d.tsum;
+  const bool isx = i < d.tx;
+  const int b0 = isx ? 0 : d.tx, b1 = isx ? d.tx : d.nt;  // own block's tile range
+  double same = 0.0, cross = 0.0;
+  for (int j = b0; j < i; ++j) same += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
+  for (int j = i; j < b1; ++j) same += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
+  if (isx) {
+    for (int j = d.tx; j < d.nt; ++j) cross += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
+  } else {
+    for (int j = 0; j < d.tx; ++j)
+      cross += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
+  }
+  d.rsum[pos * 2 + 0] = same;
+  d.rsum[pos * 2 + 1] = cross;
+}
+
+struct Neu {
+  double s, c;
+  __device__ void add(double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+  }
+  __device__ double value() const { return s + c; }
+};
+
+// One workgroup per test: S_XX, S_YY, S_XY and the observed statistic.
+__global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ descs,
+                                                  const int64_t* __restrict__ sel, int ntests) {
+  __shared__ double red[3][256][2];
+  if (sel && sel[blockIdx.x + 1] == sel[blockIdx.x]) return;
+  const TestDesc& d = descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  Neu sxx{0, 0}, syy{0, 0}, sxy{0, 0};
+  const int64_t xend = (int64_t)d.tx * TILE, npad = (int64_t)d.nt * TILE;
+  for (int64_t pos = tid; pos < npad; pos += 256) {
+    if (pos < xend) {
+      sxx.add(d.rsum[pos * 2]);
+      sxy.add(d.rsum[pos * 2 + 1]);
+    } else {
+      syy.add(d.rsum[pos * 2]);
+    }
+  }
+  red[0][tid][0] = sxx.s; red[0][tid][1] = sxx.c;
+  red[1][tid][0] = syy.s; red[1][tid][1] = syy.c;
+  red[2][tid][0] = sxy.s; red[2][tid][1] = sxy.c;
+  __syncthreads();
+  if (tid < 3) {
+    Neu a{0, 0};
+    double comp = 0.0;
+    for (int q = 0; q < 256; ++q) {
+      a.add(red[tid][q][0]);
+      comp += red[tid][q][1];
+    }
+    a.add(comp);
+    d.obs[tid] = a.value();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double nx = d.nx, ny = d.ny;
+    const double txx = d.obs[0] / (nx * nx), tyy = d.obs[1] / (ny * ny);
+    const double txy = 2.0 * d.obs[2] / (nx * ny);
+    d.obs[3] = d.kind == KIND_ED ? (txy - txx) - tyy : (txx + tyy) - txy;
+    d.obs[4] = d.obs[0] + d.obs[1] + 2.0 * d.obs[2];  // R = sum of all pooled row sums
+  }
+}
+
+void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
+  if (blocks > 0) hipLaunchKernelGGL(k_rowsum, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+}
+void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n) {
+  hipLaunchKernelGGL(k_observed, dim3((unsigned)n), dim3(256), 0, st, d, sel, n);
+}
+
+}  // namespace et

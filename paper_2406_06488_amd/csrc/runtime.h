@@ -1,0 +1,87 @@
+// Host runtime shared by the synchronous, batched and serving entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "etest.h"
+
+namespace et {
+
+// Kernel launchers (defined next to their kernels).
+void launch_clear_flags(hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_colpart(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_colmean(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_stage(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
+                 int n);
+void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
+void launch_center(bool f64, int64_t blocks, hipStream_t st, const TestDesc* d,
+                   const int64_t* offs, int n);
+void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_member_public(int64_t nx, int64_t ny, uint64_t seed, int64_t b0, int64_t count,
+                          uint32_t* words, hipStream_t st);
+void launch_member_import(int64_t bpad, hipStream_t st, const TestDesc* d, const uint32_t* w);
+void launch_perm(int variant, int64_t blocks, hipStream_t st, const TestDesc* d,
+                 const int64_t* offs, int ntests, const int32_t* pcr);
+void launch_pstat(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_final(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
+void launch_unpack(bool f64, int64_t elems, hipStream_t st, const TestDesc* d, void* xx, void* yy,
+                   void* xy);
+
+// Launch slots: one prefix array of workgroup counts per slot.
+enum Slot {
+  S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16, S_MEMBER, S_ROWSUM,
+  S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S1, S_PERM_S2, S_PERM_S3, S_PSTAT, S_COUNT
+};
+
+struct TestPlan {
+  TestDesc d{};              // sizes now, pointers once the workspace is placed
+  size_t bytes = 0;          // workspace bytes of this test
+  size_t off[16] = {};       // offsets of its buffers inside its region
+  int64_t wg[S_COUNT] = {};  // workgroups per launch slot
+};
+
+// Sets the calling thread's error message; returns the status.
+etest_status set_error(etest_status s, const std::string& msg);
+etest_status validate_request(const etest_request& r);
+TestPlan make_plan(const etest_request& r, int64_t kc_override = 0);
+
+// A set of tests laid out in one device workspace, ready to launch.
+struct Batch {
+  std::vector<TestPlan> plans;
+  std::vector<TestDesc> descs;   // with device pointers
+  std::vector<int64_t> offs;     // [S_COUNT][n + 1]
+  void* ws = nullptr;            // device workspace
+  size_t ws_bytes = 0;
+  TestDesc* d_descs = nullptr;
+  int64_t* d_offs = nullptr;
+  DevResult* d_results = nullptr;
+  double* d_perm = nullptr;      // internal perm-stat buffers (host-output calls)
+};
+
+// Point a plan's descriptor at its buffers inside a device region.
+void assign_pointers(TestPlan& P, char* region, DevResult* result);
+void init_pool_once();
+
+// Build plans + layout (host only).  extra_perm: allocate internal perm-stat
+// outputs for tests whose request has perm_stats == NULL but the caller wants them.
+etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_perm, Batch* b);
+// Allocate the workspace on `st`, copy descriptors.
+etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered);
+// Optional stage events: ev[k] is recorded before stage k, ev[NSTAGE] after the last.
+constexpr int NSTAGE = 7;
+struct StageEvents {
+  hipEvent_t ev[NSTAGE + 1];
+};
+
+// Enqueue every stage.  import_words: caller splits for a single test (or null).
+void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words = nullptr,
+                   const StageEvents* events = nullptr);
+void free_batch(Batch* b, hipStream_t st, bool stream_ordered);
+etest_status dev_to_result(const DevResult& r, etest_result* out);
+
+}  // namespace et

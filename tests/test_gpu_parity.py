@@ -1,0 +1,204 @@
+"""HIP path vs the FP64 oracle, through the C ABI, on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2406_06488_amd import api, inputs
+from paper_2406_06488_amd._lib import EtestError
+from tests.gpu_helpers import TOL, compare_run, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+KIND = {"ed": oracle.ED, "mmd": oracle.MMD}
+
+
+def _dev(a, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dt)
+
+
+def _data(nx, ny, p, seed, prec, shift=0.1):
+    dt = np.float64 if prec == "f64" else np.float32
+    return inputs.gaussian_pair(nx, ny, p, seed, mean_shift=shift, dtype=dt)
+
+
+# --------------------------------------------------------------------------- split stream
+
+@pytest.mark.parametrize("nx,ny,seed,b0,count", [(5, 4, 0, 0, 300), (100, 100, 1, 0, 1000),
+                                                 (33, 64, 123456789, 2 ** 32 - 5, 40),
+                                                 (1, 1, 3, 0, 10), (300, 170, 9, 50, 257),
+                                                 (127, 129, 2 ** 63 + 7, 1000, 33)])
+def test_membership_bit_exact(nx, ny, seed, b0, count):
+    say("membership", nx, ny, seed, b0, count)
+    words = api.membership(nx, ny, seed, b0, count)
+    torch.cuda.synchronize()
+    Z = api.unpack_words(words, nx + ny)
+    for q in range(count):
+        assert np.array_equal(Z[q], oracle.membership(nx, ny, seed, b0 + q)), q
+
+
+# --------------------------------------------------------------------------- blocks
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+def test_blocks_against_direct_differences(prec, kind):
+    nx, ny, p = 300, 170, 37
+    say("blocks", prec, kind, nx, ny, p)
+    X, Y = _data(nx, ny, p, 5, prec)
+    gamma = 1.0 / p
+    dxx, dyy, dxy = api.blocks(_dev(X, prec), _dev(Y, prec), kind, prec, gamma)
+    torch.cuda.synchronize()
+    oxx, oyy, oxy = oracle.blocks(X, Y, KIND[kind], gamma)
+    tol = {"f64": 1e-13, "f32": 3e-6, "bf16r": 2e-2}[prec]
+    for g, o in ((dxx, oxx), (dyy, oyy), (dxy, oxy)):
+        g = g.double().cpu().numpy()
+        scale = np.abs(o).max()
+        assert np.abs(g - o).max() <= tol * scale, (prec, kind, np.abs(g - o).max(), scale)
+    diag = 0.0 if kind == "ed" else 1.0
+    assert np.all(np.diag(dxx.double().cpu().numpy()) == diag)
+    assert np.all(np.diag(dyy.double().cpu().numpy()) == diag)
+
+
+# --------------------------------------------------------------------------- whole test
+
+CASES = [
+    # nx, ny, p, B, data seed, perm seed, shift
+    (100, 100, 10, 1000, 0, 1, 0.0),     # the small FP64 null workload
+    (300, 170, 37, 700, 3, 5, 0.15),     # several tiles, ragged tails, B_pad > one chunk
+    (129, 127, 64, 255, 4, 6, 0.3),      # one row past a tile / one short
+    (1, 5, 3, 40, 5, 7, 0.5),
+    (7, 1, 2, 40, 6, 8, 0.5),
+    (1, 1, 4, 20, 7, 9, 1.0),
+    (40, 33, 1, 300, 8, 10, 0.2),        # p = 1
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_full_test_matches_oracle(case, kind, prec):
+    nx, ny, p, B, ds, ps_, shift = CASES[case]
+    say("full", case, kind, prec, nx, ny, p, B)
+    if prec == "bf16r" and p < 8:
+        pytest.skip("BF16 Gram on a handful of coordinates is outside its tolerance design")
+    X, Y = _data(nx, ny, p, ds, prec, shift)
+    gamma = 1.0 / p
+    g = api.run(_dev(X, prec), _dev(Y, prec), B, ps_, kind, prec, gamma)
+    torch.cuda.synchronize()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, ps_, KIND[kind], gamma)
+    near = compare_run(g, o, prec, "case %d %s %s" % (case, kind, prec))
+    if len(near):
+        say("near-ties within tolerance:", near.tolist())
+
+
+def test_zero_and_one_permutations():
+    X, Y = _data(20, 30, 5, 1, "f32")
+    g = api.run(_dev(X, "f32"), _dev(Y, "f32"), 0, 1, "ed", "f32")
+    assert g["p_value"] == 1.0 and g["count_ge"] == 0 and g["B"] == 0
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), 1, 1)
+    g = api.run(_dev(X, "f32"), _dev(Y, "f32"), 1, 1, "ed", "f32")
+    compare_run(g, o, "f32")
+
+
+def test_nonfinite_input_rejected_and_outputs_untouched():
+    X, Y = _data(50, 40, 6, 2, "f32")
+    X[3, 2] = np.nan
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    ps = torch.full((100,), 7.0, dtype=torch.float64, device=DEV)
+    req = api.make_request(Xd, Yd, 100, 1, "ed", "f32", 0.0, ps)
+    import ctypes
+    from paper_2406_06488_amd import _lib
+    r = _lib.Result()
+    st = _lib.load().etest_run(ctypes.byref(req), None, ctypes.byref(r))
+    assert st == _lib.ENONFINITE
+    assert torch.all(ps == 7.0)
+    Y[0, 0] = np.inf
+    with pytest.raises(EtestError):
+        api.ed_test(X, Y, 10, 1, "f32")
+
+
+def test_repeat_runs_bit_identical():
+    X, Y = _data(300, 200, 50, 9, "f32")
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    a = api.run(Xd, Yd, 1000, 3, "ed", "bf16r")
+    b = api.run(Xd, Yd, 1000, 3, "ed", "bf16r")
+    assert torch.equal(a["perm_stats"], b["perm_stats"])
+    assert a["statistic"] == b["statistic"] and a["threshold"] == b["threshold"]
+
+
+def test_batch_equals_alone():
+    specs = [(120, 90, 20, 300, "ed", "f32"), (60, 200, 100, 500, "mmd", "bf16r"),
+             (300, 170, 37, 257, "ed", "f64"), (5, 4, 3, 100, "mmd", "f32"),
+             (700, 650, 64, 1000, "ed", "bf16r")]
+    reqs, keep, alone = [], [], []
+    for t, (nx, ny, p, B, kind, prec) in enumerate(specs):
+        X, Y = _data(nx, ny, p, 100 + t, prec)
+        Xd, Yd = _dev(X, prec), _dev(Y, prec)
+        ps = torch.zeros(B, dtype=torch.float64, device=DEV)
+        keep += [Xd, Yd, ps]
+        reqs.append(api.make_request(Xd, Yd, B, 200 + t, kind, prec, 1.0 / p, ps))
+        alone.append(api.run(Xd, Yd, B, 200 + t, kind, prec, 1.0 / p))
+    for rep in range(2):  # second call replays the captured graph
+        outs = api.batch(reqs)
+        torch.cuda.synchronize()
+        for t in range(len(specs)):
+            for k in ("statistic", "threshold", "count_ge", "p_value"):
+                assert outs[t][k] == alone[t][k], (rep, t, k)
+            assert torch.equal(keep[3 * t + 2], alone[t]["perm_stats"]), (rep, t)
+
+
+def test_enumeration_through_supplied_splits():
+    """nx = ny = 5: all 252 splits evaluated on the GPU equal the oracle's table; the
+    identity equals the threshold and its complement ties with it."""
+    nx = ny = 5
+    X, Y = _data(nx, ny, 4, 31, "f64", 0.6)
+    splits = np.array(list(brute.all_splits(nx, ny)), dtype=np.uint8)
+    words = torch.from_numpy(api.pack_splits(splits)).to(DEV)
+    for kind in ("ed", "mmd"):
+        g = api.perm_stats_from_membership(_dev(X, "f64"), _dev(Y, "f64"), words, kind, "f64", 0.25)
+        torch.cuda.synchronize()
+        gs = g["perm_stats"].cpu().numpy()
+        XX, YY, XY = oracle.blocks(X, Y, KIND[kind], 0.25)
+        want = np.array([oracle.perm_stat(XX, YY, XY, z, KIND[kind]) for z in splits])
+        assert np.all(np.abs(gs - want) <= 1e-12 * np.abs(want))
+        ident = np.flatnonzero((splits[:, :nx] == 1).all(axis=1))[0]
+        assert abs(gs[ident] - g["threshold"]) <= 1e-12 * abs(g["threshold"])
+
+
+def test_supplied_split_with_wrong_size_rejected():
+    X, Y = _data(6, 5, 3, 1, "f32")
+    Z = np.zeros((1, 11), dtype=np.uint8)
+    Z[0, :5] = 1  # five members instead of six
+    words = torch.from_numpy(api.pack_splits(Z)).to(DEV)
+    with pytest.raises(EtestError):
+        api.perm_stats_from_membership(_dev(X, "f32"), _dev(Y, "f32"), words, "ed", "f32")
+
+
+def test_host_buffer_calls_match_device_calls():
+    X, Y = _data(210, 190, 30, 12, "f32")
+    h = api.ed_test(X, Y, 500, 4, "f32")
+    d = api.run(_dev(X, "f32"), _dev(Y, "f32"), 500, 4, "ed", "f32")
+    assert h["statistic"] == d["statistic"] and h["count_ge"] == d["count_ge"]
+    assert np.array_equal(h["perm_stats"], d["perm_stats"].cpu().numpy())
+    h = api.mmd_test(X, Y, 0.05, 500, 4, "bf16r")
+    d = api.run(_dev(X, "f32"), _dev(Y, "f32"), 500, 4, "mmd", "bf16r", 0.05)
+    assert h["statistic"] == d["statistic"] and h["count_ge"] == d["count_ge"]
+    X64, Y64 = _data(50, 60, 5, 13, "f64")
+    h = api.ed_test(X64, Y64, 300, 4, "f64")
+    o = oracle.run_test(X64, Y64, 300, 4)
+    compare_run(h, o, "f64")
+
+
+def test_async_call_matches_sync():
+    X, Y = _data(150, 140, 20, 14, "f32")
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    ps = torch.zeros(400, dtype=torch.float64, device=DEV)
+    buf = api.run_async(Xd, Yd, 400, 9, "mmd", "f32", 0.05, ps)
+    torch.cuda.synchronize()
+    a = api.result_from_device(buf)
+    s = api.run(Xd, Yd, 400, 9, "mmd", "f32", 0.05)
+    assert a["statistic"] == s["statistic"] and a["count_ge"] == s["count_ge"]
+    assert torch.equal(ps, s["perm_stats"])
