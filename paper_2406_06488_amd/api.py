@@ -220,6 +220,63 @@ def last_error():
     return _lib.load().etest_last_error().decode()
 
 
+class Server:
+    """Continuous-batching server over the C ABI.  Requests reference device tensors that
+    must stay alive until the request completes (this wrapper keeps them)."""
+
+    def __init__(self, memory_budget_bytes=32 << 30, max_resident=64, max_queue=1 << 20,
+                 chunk_updates=0):
+        cfg = _lib.ServerConfig(memory_budget_bytes, max_resident, max_queue, chunk_updates)
+        self._h = ctypes.c_void_p()
+        check(_lib.load().etest_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, X, Y, B, seed, kind="ed", prec="bf16r", gamma=0.0, perm_stats=None):
+        """Queue one test; returns its id.  perm_stats: float64 device tensor of B or None."""
+        _check_dev(X, Y, prec)
+        req = make_request(X, Y, B, seed, kind, prec, gamma, perm_stats)
+        rid = ctypes.c_uint64()
+        check(_lib.load().etest_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._keep[rid.value] = (X, Y, perm_stats)
+        return rid.value
+
+    def poll(self, rid):
+        """Result dict when finished, None while running."""
+        r = Result()
+        st = _lib.load().etest_server_poll(self._h, rid, ctypes.byref(r))
+        if st == _lib.EBUSY:
+            return None
+        self._keep.pop(rid, None)
+        check(st)
+        return r.as_dict()
+
+    def wait(self, rid):
+        r = Result()
+        st = _lib.load().etest_server_wait(self._h, rid, ctypes.byref(r))
+        self._keep.pop(rid, None)
+        check(st)
+        return r.as_dict()
+
+    def stats(self):
+        q, res, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(_lib.load().etest_server_stats(self._h, ctypes.byref(q), ctypes.byref(res),
+                                             ctypes.byref(b), ctypes.byref(c)))
+        return {"queued": q.value, "resident": res.value, "bytes_held": b.value,
+                "completed": c.value}
+
+    def close(self):
+        if self._h:
+            check(_lib.load().etest_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def profile_enable(on=True):
     check(_lib.load().etest_profile_enable(1 if on else 0))
 

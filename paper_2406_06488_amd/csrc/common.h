@@ -24,7 +24,8 @@ namespace et {
 
 constexpr int TILE = 128;            // edge of a stored block tile
 constexpr int TILE_WORDS = TILE / 32;
-constexpr int NP = 256;              // split columns per resampling workgroup
+constexpr int NP = 256;              // split columns per resampling chunk
+constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
 enum { KIND_ED = 0, KIND_MMD = 1 };
@@ -40,7 +41,7 @@ struct TestDesc {
   int32_t kind, prec, splits, refine;
   int32_t nx, ny, p, p_pad;
   int32_t tx, ty, nt, ntiles;
-  int32_t kc, n_rowk, nrowchunks, pad0;
+  int32_t kc, n_rowk, nrowchunks, cc;  // cc: split-column chunks per resampling workgroup
   int64_t B, B_pad;
   uint64_t seed;
   double gamma;

@@ -66,41 +66,95 @@ struct SplitDraw {
 
 // Internal layout Z[w][col]: columns 0..B-1 drawn splits, B the identity split,
 // the rest zero; words cover padded pooled positions (X tiles, then Y tiles).
+//
+// One workgroup serves MSPL consecutive split columns.  The scaled draws
+// v_t = floor(u_t (n - t) / 2^64) do not depend on the running count, so they
+// are produced in parallel, a chunk of MCH items at a time, into LDS; wave 0
+// then runs the selection scan (one lane per split) over the chunk while waves
+// 1-3 draw the next chunk.
+constexpr int MCH = 64;
+constexpr int MSPL = 64;
+
+__device__ inline uint32_t scaled_draw(uint32_t lo, uint32_t hi, uint32_t m) {
+  const uint64_t p_lo = (uint64_t)lo * m, p_hi = (uint64_t)hi * m;
+  return (uint32_t)((p_hi + (p_lo >> 32)) >> 32);  // floor(u * m / 2^64), u = hi:lo
+}
+
 __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ offs, int ntests) {
+  __shared__ uint32_t V[2][MCH][MSPL];
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc& d = descs[ti];
-  const int64_t col = (blockIdx.x - offs[ti]) * 256 + threadIdx.x;
-  if (col >= d.B_pad) return;
+  const int64_t col0 = (blockIdx.x - offs[ti]) * MSPL;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t n = (int64_t)d.nx + d.ny;
+  const int xw = d.tx * TILE_WORDS, nwords = d.nt * TILE_WORDS;
+  const int64_t ybase = (int64_t)d.tx * TILE;
   uint32_t* Z = d.Z;
-  const int xw = d.tx * TILE_WORDS, yw = d.ty * TILE_WORDS;
-  if (col >= d.B) {
-    const bool ident = col == d.B;
-    for (int w = 0; w < xw; ++w) {
-      uint32_t word = 0;
-      if (ident) {
-        const int lo = w * 32;
-        const int cnt = d.nx - lo;
-        word = cnt >= 32 ? 0xFFFFFFFFu : (cnt > 0 ? ((1u << cnt) - 1u) : 0u);
+  // words that hold no item, and the non-drawn columns (identity / padding)
+  for (int64_t e = tid; e < (int64_t)nwords * MSPL; e += 256) {
+    const int w = (int)(e / MSPL);
+    const int64_t c = col0 + e % MSPL;
+    const bool gap = w < xw ? (int64_t)w * 32 >= d.nx : (int64_t)(w - xw) * 32 >= d.ny;
+    if (c >= d.B) {
+      uint32_t v = 0;
+      if (c == d.B && w < xw) {
+        const int64_t cnt = d.nx - (int64_t)w * 32;
+        v = cnt >= 32 ? 0xFFFFFFFFu : (cnt > 0 ? ((1u << cnt) - 1u) : 0u);
       }
-      Z[(int64_t)w * d.B_pad + col] = word;
+      Z[(int64_t)w * d.B_pad + c] = v;
+    } else if (gap) {
+      Z[(int64_t)w * d.B_pad + c] = 0u;
     }
-    for (int w = 0; w < yw; ++w) Z[(int64_t)(xw + w) * d.B_pad + col] = 0u;
-    return;
   }
-  SplitDraw s(d.seed, (uint64_t)col, d.nx, d.ny);
-  for (int w = 0; w < xw; ++w) {
-    uint32_t word = 0;
-    for (int bit = 0; bit < 32; ++bit)
-      if (w * 32 + bit < d.nx) word |= s.next() << bit;
-    Z[(int64_t)w * d.B_pad + col] = word;
+  if (col0 >= d.B) return;
+  const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
+  const int nch = (int)((n + MCH - 1) / MCH);
+  auto draw_chunk = [&](int ch, int buf, int first, int stride) {
+    for (int q = first; q < (MCH / 2) * MSPL; q += stride) {
+      const int s = q % MSPL, bi = q / MSPL;
+      const int64_t t = (int64_t)ch * MCH + 2 * bi;
+      const uint64_t bb = (uint64_t)(col0 + s);
+      if (t >= n || (int64_t)bb >= d.B) continue;
+      const uint4 r = philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)bb,
+                                               (uint32_t)(bb >> 32), 0u), k0, k1);
+      V[buf][2 * bi][s] = scaled_draw(r.x, r.y, (uint32_t)(n - t));
+      if (t + 1 < n) V[buf][2 * bi + 1][s] = scaled_draw(r.z, r.w, (uint32_t)(n - t - 1));
+    }
+  };
+  draw_chunk(0, 0, tid, 256);
+  __syncthreads();
+  const int64_t b = col0 + lane;
+  const bool drawn = b < d.B;
+  int64_t need = d.nx, wcur = -1;
+  uint32_t word = 0;
+  for (int ch = 0; ch < nch; ++ch) {
+    if (wave != 0) {
+      if (ch + 1 < nch) draw_chunk(ch + 1, (ch + 1) & 1, tid - 64, 192);
+    } else if (drawn) {
+      const int64_t t0 = (int64_t)ch * MCH;
+      for (int k = 0; k < MCH; ++k) {
+        const int64_t t = t0 + k;
+        if (t >= n) break;
+        const int64_t m = n - t;
+        uint32_t take;
+        if (need == 0) take = 0;
+        else if (need == m) take = 1;
+        else take = (int64_t)V[ch & 1][k][lane] < need ? 1u : 0u;
+        need -= take;
+        const int64_t pos = t < d.nx ? t : ybase + (t - d.nx);
+        const int64_t w = pos >> 5;
+        if (w != wcur) {
+          if (wcur >= 0) Z[wcur * d.B_pad + b] = word;
+          word = 0;
+          wcur = w;
+        }
+        word |= take << (pos & 31);
+      }
+    }
+    __syncthreads();
   }
-  for (int w = 0; w < yw; ++w) {
-    uint32_t word = 0;
-    for (int bit = 0; bit < 32; ++bit)
-      if (w * 32 + bit < d.ny) word |= s.next() << bit;
-    Z[(int64_t)(xw + w) * d.B_pad + col] = word;
-  }
+  if (wave == 0 && drawn && wcur >= 0) Z[wcur * d.B_pad + b] = word;
 }
 
 // Public layout: words[(b - b0) * W + t / 32], bit t % 32, W = ceil(n / 32).
@@ -120,6 +174,7 @@ __global__ void __launch_bounds__(256) k_member_public(int64_t nx, int64_t ny, u
   }
 }
 
+// blocks: split columns / MSPL workgroups per test
 void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
   if (blocks > 0) hipLaunchKernelGGL(k_member, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
 }

@@ -55,9 +55,6 @@ etest_status validate_request(const etest_request& r) {
   return ETEST_OK;
 }
 
-// Buffer ids inside one test's region.
-enum Buf { B_COLPART, B_COLMEAN, B_W, B_NRM, B_D, B_TSUM, B_RSUM, B_OBS, B_PLANES, B_Z, B_PART,
-           B_PSTAT, B_FLAGS, B_RESULT, B_PERMOUT, B_NBUF };
 
 TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   TestPlan P;
@@ -75,7 +72,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.ntiles = d.nt * (d.nt + 1) / 2;
   d.splits = r.prec == ETEST_PREC_F32 ? 3
              : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 3) : 1;
-  d.refine = r.prec == ETEST_PREC_BF16_REFINED ? 1 : 0;
+  d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
   d.kc = (int32_t)(kc_override > 0 ? kc_override : 8);
   int nrk = 0;
   for (int i = 0; i < d.nt; ++i) nrk += (d.nt - i + d.kc - 1) / d.kc;
@@ -84,6 +81,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.nrowchunks = (int32_t)((n + 127) / 128);
   d.B = r.B;
   d.B_pad = (r.B + 1 + NP - 1) / NP * NP;
+  d.cc = (int32_t)std::min<int64_t>(env_int("ETEST_CC", 4, 1, MAX_CC), d.B_pad / NP);
   d.seed = r.seed;
   d.gamma = r.kind == ETEST_MMD ? r.gamma : 0.0;
   d.X = r.X;
@@ -112,11 +110,13 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   sz[B_RESULT] = sizeof(DevResult);
   sz[B_PERMOUT] = 0;  // set by build_batch when an internal output is needed
   size_t o = 0;
-  for (int k = 0; k < B_NBUF; ++k) {
+  for (int k = 0; k < B_PERMOUT; ++k) {
     P.off[k] = o;
+    P.size[k] = sz[k];
     o += align256(sz[k]);
   }
   P.bytes = o;
+  P.internal_perm = false;  // build_batch appends an internal output buffer when asked
 
   const bool f32like = !f64;
   P.wg[S_COLPART] = f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0;
@@ -125,11 +125,11 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
   P.wg[S_GRAM_F32] = r.prec == ETEST_PREC_F32 ? d.ntiles : 0;
   P.wg[S_GRAM_BF16] = r.prec == ETEST_PREC_BF16_REFINED ? d.ntiles : 0;
-  P.wg[S_MEMBER] = d.B_pad / 256;
+  P.wg[S_MEMBER] = d.B_pad / 64;  // 64 split columns per workgroup
   P.wg[S_ROWSUM] = (npad + 255) / 256;
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
   P.wg[S_CENTER_SPLIT] = f64 ? 0 : d.ntiles;
-  const int64_t perm_wg = (int64_t)d.n_rowk * (d.B_pad / NP);
+  const int64_t perm_wg = perm_units(d, (int)(d.B_pad / NP));
   P.wg[S_PERM_F64] = f64 ? perm_wg : 0;
   P.wg[S_PERM_S1] = (!f64 && d.splits == 1) ? perm_wg : 0;
   P.wg[S_PERM_S2] = (!f64 && d.splits == 2) ? perm_wg : 0;
@@ -147,7 +147,9 @@ etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_per
     TestPlan P = make_plan(reqs[t]);
     if (internal_perm && reqs[t].perm_stats == nullptr && reqs[t].B > 0) {
       P.off[B_PERMOUT] = P.bytes;
+      P.size[B_PERMOUT] = (size_t)reqs[t].B * 8;
       P.bytes += align256((size_t)reqs[t].B * 8);
+      P.internal_perm = true;
     }
     b->plans.push_back(P);
   }
@@ -170,7 +172,9 @@ void assign_pointers(TestPlan& P, char* r, DevResult* result) {
   d.pstat = (double*)(r + P.off[B_PSTAT]);
   d.flags = (int32_t*)(r + P.off[B_FLAGS]);
   d.result = result;
-  if (P.off[B_PERMOUT] != 0 && d.perm_out == nullptr) d.perm_out = (double*)(r + P.off[B_PERMOUT]);
+  // perm_out stays the caller's pointer (possibly NULL: no per-split output) unless an
+  // internal output buffer was appended to this test's region
+  if (P.internal_perm) d.perm_out = (double*)(r + P.off[B_PERMOUT]);
 }
 
 etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered) {
@@ -224,41 +228,73 @@ void free_batch(Batch* b, hipStream_t st, bool stream_ordered) {
 }
 
 void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
-                   const StageEvents* ev) {
+                   const StageEvents* ev, const Fork* fork) {
   const int n = (int)b.plans.size();
   auto offs = [&](Slot s) { return b.d_offs + (size_t)s * (n + 1); };
   auto total = [&](Slot s) { return b.offs[(size_t)s * (n + 1) + n]; };
-  auto mark = [&](int k) {
-    if (ev) (void)hipEventRecord(ev->ev[k], st);
+  auto begin = [&](int k, hipStream_t s) {
+    if (ev) (void)hipEventRecord(ev->begin[k], s);
+  };
+  auto end = [&](int k, hipStream_t s) {
+    if (ev) (void)hipEventRecord(ev->end[k], s);
   };
   const TestDesc* D = b.d_descs;
-  mark(0);
   launch_clear_flags(st, D, nullptr, n);
+  // split stream: independent of the data, so it may run beside the block stage
+  hipStream_t ms = st;
+  if (fork) {
+    (void)hipEventRecord(fork->start, st);
+    (void)hipStreamWaitEvent(fork->aux, fork->start, 0);
+    ms = fork->aux;
+  }
+  begin(2, ms);
+  if (import_words) launch_member_import(b.plans[0].d.B_pad, ms, D, import_words);
+  else launch_member(total(S_MEMBER), ms, D, offs(S_MEMBER), n);
+  end(2, ms);
+  if (fork) (void)hipEventRecord(fork->done, ms);
+  begin(0, st);
   launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), n);
   launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), n);
   launch_stage(total(S_STAGE), st, D, offs(S_STAGE), n);
-  mark(1);
+  end(0, st);
+  begin(1, st);
   launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n);
   launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n);
   launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n);
-  mark(2);
-  if (import_words) launch_member_import(b.plans[0].d.B_pad, st, D, import_words);
-  else launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), n);
-  mark(3);
+  end(1, st);
+  begin(3, st);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), n);
   launch_observed(st, D, nullptr, n);
-  mark(4);
+  end(3, st);
+  begin(4, st);
   launch_center(true, total(S_CENTER_F64), st, D, offs(S_CENTER_F64), n);
   launch_center(false, total(S_CENTER_SPLIT), st, D, offs(S_CENTER_SPLIT), n);
-  mark(5);
+  end(4, st);
+  if (fork) (void)hipStreamWaitEvent(st, fork->done, 0);
+  begin(5, st);
   launch_perm(0, total(S_PERM_F64), st, D, offs(S_PERM_F64), n, nullptr);
   launch_perm(1, total(S_PERM_S1), st, D, offs(S_PERM_S1), n, nullptr);
   launch_perm(2, total(S_PERM_S2), st, D, offs(S_PERM_S2), n, nullptr);
   launch_perm(3, total(S_PERM_S3), st, D, offs(S_PERM_S3), n, nullptr);
-  mark(6);
+  end(5, st);
+  begin(6, st);
   launch_pstat(total(S_PSTAT), st, D, offs(S_PSTAT), n);
   launch_final(st, D, nullptr, n);
-  mark(7);
+  end(6, st);
+}
+
+// Per-thread auxiliary stream and fork/join events.
+static const Fork* thread_fork() {
+  static thread_local Fork f;
+  static thread_local int state = 0;  // 0 untried, 1 ready, -1 unavailable
+  if (state == 0) {
+    state = -1;
+    if (hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&f.start, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess)
+      state = 1;
+  }
+  return state == 1 ? &f : nullptr;
 }
 
 // ------------------------------------------------------------------ stage timing
@@ -274,8 +310,10 @@ static thread_local Profile g_prof;
 static const StageEvents* profile_events() {
   if (!g_prof.on) return nullptr;
   if (!g_prof.ready) {
-    for (int k = 0; k <= NSTAGE; ++k)
-      if (hipEventCreate(&g_prof.ev.ev[k]) != hipSuccess) return nullptr;
+    for (int k = 0; k < NSTAGE; ++k)
+      if (hipEventCreate(&g_prof.ev.begin[k]) != hipSuccess ||
+          hipEventCreate(&g_prof.ev.end[k]) != hipSuccess)
+        return nullptr;
     g_prof.ready = true;
   }
   return &g_prof.ev;
@@ -286,7 +324,7 @@ static void profile_collect() {
   if (!g_prof.on || !g_prof.ready) return;
   for (int k = 0; k < NSTAGE; ++k) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, g_prof.ev.ev[k], g_prof.ev.ev[k + 1]) == hipSuccess) {
+    if (hipEventElapsedTime(&ms, g_prof.ev.begin[k], g_prof.ev.end[k]) == hipSuccess) {
       g_prof.ms[k] += ms;
       g_prof.launches[k] += 1;
     }
@@ -342,7 +380,7 @@ static etest_status run_device(const etest_request* reqs, int64_t n, hipStream_t
   if (s != ETEST_OK) return s;
   s = place_batch(&b, st, true);
   if (s != ETEST_OK) return s;
-  enqueue_batch(b, st, import_words, profile_events());
+  enqueue_batch(b, st, import_words, profile_events(), thread_fork());
   hipError_t e = hipGetLastError();
   DevResult* hr = pinned_results((size_t)n);
   if (e == hipSuccess && hr)
@@ -467,7 +505,7 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
     HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      enqueue_batch(g.batch, cap);
+      enqueue_batch(g.batch, cap, nullptr, nullptr, thread_fork());
       e = hipStreamEndCapture(cap, &g.graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);

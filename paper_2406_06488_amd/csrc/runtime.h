@@ -32,16 +32,28 @@ void launch_final(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
 void launch_unpack(bool f64, int64_t elems, hipStream_t st, const TestDesc* d, void* xx, void* yy,
                    void* xy);
 
+// Resampling workgroups of a test for pcn split-column chunks: one per (row range,
+// group of up to cc chunks).
+inline int64_t perm_units(const TestDesc& d, int pcn) {
+  return (int64_t)d.n_rowk * ((pcn + d.cc - 1) / d.cc);
+}
+
 // Launch slots: one prefix array of workgroup counts per slot.
 enum Slot {
   S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16, S_MEMBER, S_ROWSUM,
   S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S1, S_PERM_S2, S_PERM_S3, S_PSTAT, S_COUNT
 };
 
+// Buffer ids inside one test's region.
+enum Buf { B_COLPART, B_COLMEAN, B_W, B_NRM, B_D, B_TSUM, B_RSUM, B_OBS, B_PLANES, B_Z, B_PART,
+           B_PSTAT, B_FLAGS, B_RESULT, B_PERMOUT, B_NBUF };
+
 struct TestPlan {
   TestDesc d{};              // sizes now, pointers once the workspace is placed
   size_t bytes = 0;          // workspace bytes of this test
   size_t off[16] = {};       // offsets of its buffers inside its region
+  size_t size[16] = {};      // their sizes in bytes
+  bool internal_perm = false;  // per-split output lives in the region (off[B_PERMOUT])
   int64_t wg[S_COUNT] = {};  // workgroups per launch slot
 };
 
@@ -72,15 +84,22 @@ void init_pool_once();
 etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_perm, Batch* b);
 // Allocate the workspace on `st`, copy descriptors.
 etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered);
-// Optional stage events: ev[k] is recorded before stage k, ev[NSTAGE] after the last.
+// Optional stage events: begin[k] / end[k] bracket stage k on the stream it runs on.
 constexpr int NSTAGE = 7;
 struct StageEvents {
-  hipEvent_t ev[NSTAGE + 1];
+  hipEvent_t begin[NSTAGE], end[NSTAGE];
+};
+
+// Optional second stream for the split stream, which does not depend on the data:
+// it is forked after the descriptor copy and joined before the resampling stage.
+struct Fork {
+  hipStream_t aux;
+  hipEvent_t start, done;
 };
 
 // Enqueue every stage.  import_words: caller splits for a single test (or null).
 void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words = nullptr,
-                   const StageEvents* events = nullptr);
+                   const StageEvents* events = nullptr, const Fork* fork = nullptr);
 void free_batch(Batch* b, hipStream_t st, bool stream_ordered);
 etest_status dev_to_result(const DevResult& r, etest_result* out);
 

@@ -300,7 +300,7 @@ void run_scheduler(etest_server* S) {
         take = std::min(take, left);
         S->h_pcr[2 * k] = q->pc_done;
         S->h_pcr[2 * k + 1] = take;
-        const int64_t units = (int64_t)P.d.n_rowk * take;
+        const int64_t units = perm_units(P.d, take);
         for (int s : {S_PERM_F64, S_PERM_S1, S_PERM_S2, S_PERM_S3})
           if (P.wg[s] > 0) w[s] = units;
         q->pc_done += take;

@@ -1,0 +1,117 @@
+// Host-only check of the workspace planner: for many request shapes, every buffer of a
+// test lies inside its region, buffers do not overlap, sizes cover what the kernels index,
+// and the per-split output pointer is the caller's (NULL stays NULL) unless an internal
+// buffer was requested.  Kernel launchers are stubbed out: nothing touches a device.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "runtime.h"
+
+namespace et {
+void launch_clear_flags(hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_colpart(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_colmean(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_stage(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_gram(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_rowsum(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_observed(hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_center(bool, int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_member(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_member_public(int64_t, int64_t, uint64_t, int64_t, int64_t, uint32_t*, hipStream_t) {}
+void launch_member_import(int64_t, hipStream_t, const TestDesc*, const uint32_t*) {}
+void launch_perm(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int, const int32_t*) {}
+void launch_pstat(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_final(hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_unpack(bool, int64_t, hipStream_t, const TestDesc*, void*, void*, void*) {}
+}  // namespace et
+
+using namespace et;
+
+static int failures = 0;
+#define CHECK(c, ...)                        \
+  do {                                       \
+    if (!(c)) {                              \
+      std::printf("FAIL %s: ", #c);          \
+      std::printf(__VA_ARGS__);              \
+      std::printf("\n");                     \
+      ++failures;                            \
+    }                                        \
+  } while (0)
+
+static void check_plan(const etest_request& r, bool internal) {
+  Batch b;
+  etest_status s = build_batch(&r, 1, internal, &b);
+  CHECK(s == ETEST_OK, "build_batch %d", (int)s);
+  if (s != ETEST_OK) return;
+  TestPlan P = b.plans[0];
+  const TestDesc& d0 = P.d;
+  const int64_t npad = (int64_t)d0.nt * TILE;
+  // what the kernels index, in bytes
+  const bool f64 = r.prec == ETEST_PREC_F64;
+  size_t need[B_NBUF] = {};
+  need[B_W] = (size_t)npad * d0.p_pad * (f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2));
+  need[B_D] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 4);
+  need[B_PLANES] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 2 * d0.splits);
+  need[B_Z] = (size_t)d0.nt * TILE_WORDS * d0.B_pad * 4;
+  need[B_PART] = (size_t)d0.n_rowk * d0.B_pad * 8;
+  need[B_PSTAT] = (size_t)d0.B_pad * 8;
+  need[B_RSUM] = (size_t)npad * 16;
+  need[B_TSUM] = (size_t)d0.ntiles * 2 * TILE * 8;
+  for (int k = 0; k < B_NBUF; ++k) {
+    if (k == B_PERMOUT && !P.internal_perm) continue;
+    CHECK(P.size[k] >= need[k], "buffer %d: %zu < %zu", k, P.size[k], need[k]);
+    CHECK(P.off[k] + P.size[k] <= P.bytes, "buffer %d ends at %zu past %zu", k,
+          P.off[k] + P.size[k], P.bytes);
+    for (int m = 0; m < k; ++m) {
+      if (m == B_PERMOUT && !P.internal_perm) continue;
+      if (P.size[k] == 0 || P.size[m] == 0) continue;
+      const bool apart = P.off[k] + P.size[k] <= P.off[m] || P.off[m] + P.size[m] <= P.off[k];
+      CHECK(apart, "buffers %d and %d overlap", k, m);
+    }
+  }
+  CHECK(d0.B_pad % NP == 0 && d0.B_pad >= d0.B + 1, "B_pad %lld", (long long)d0.B_pad);
+  CHECK(d0.cc >= 1 && d0.cc <= MAX_CC, "cc %d", d0.cc);
+  // pointer assignment inside a fake region (pure address arithmetic, never dereferenced)
+  char* base = (char*)(uintptr_t)0x10000000000ull;
+  DevResult res;
+  assign_pointers(P, base, &res);
+  if (P.internal_perm) {
+    CHECK((char*)P.d.perm_out >= base && (char*)P.d.perm_out + r.B * 8 <= base + P.bytes,
+          "internal perm_out outside the region");
+  } else {
+    CHECK(P.d.perm_out == r.perm_stats, "perm_out changed from the caller's pointer");
+  }
+  CHECK((char*)P.d.Z >= base && (char*)P.d.Z + need[B_Z] <= base + P.bytes, "Z outside");
+  CHECK((char*)P.d.part >= base && (char*)P.d.part + need[B_PART] <= base + P.bytes,
+        "part outside");
+}
+
+int main() {
+  const int precs[3] = {ETEST_PREC_F64, ETEST_PREC_F32, ETEST_PREC_BF16_REFINED};
+  const int64_t shapes[][4] = {{1, 1, 1, 0},       {1, 5, 3, 40},       {100, 100, 10, 1000},
+                               {129, 127, 64, 255}, {2000, 2000, 1000, 10000},
+                               {5000, 4000, 4096, 10000}, {20000, 20000, 2000, 10000},
+                               {7, 300, 2, 1},      {50, 1500, 500, 2000}};
+  for (const auto& sh : shapes)
+    for (int prec : precs)
+      for (int kind = 0; kind < 2; ++kind)
+        for (int internal = 0; internal < 2; ++internal)
+          for (int with_out = 0; with_out < 2; ++with_out) {
+            etest_request r{};
+            r.kind = kind;
+            r.prec = prec;
+            r.nx = sh[0];
+            r.ny = sh[1];
+            r.p = sh[2];
+            r.B = sh[3];
+            r.seed = 1;
+            r.gamma = 0.5;
+            r.X = (const void*)0x1000;
+            r.Y = (const void*)0x2000;
+            r.perm_stats = with_out ? (double*)0x3000 : nullptr;
+            check_plan(r, internal != 0);
+          }
+  std::printf("%s (%d failures)\n", failures ? "FAILED" : "ok", failures);
+  return failures ? 1 : 0;
+}
