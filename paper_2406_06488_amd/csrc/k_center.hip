@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
                                                       const int64_t* __restrict__ offs,
                                                       int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int t = (int)(blockIdx.x - offs[ti]);
   int i, j;
   tile_coords(t, d.nt, &i, &j);
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
 __global__ void __launch_bounds__(256) k_center_f64(const TestDesc* __restrict__ descs,
                                                     const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int t = (int)(blockIdx.x - offs[ti]);
   int i, j;
   tile_coords(t, d.nt, &i, &j);

@@ -12,7 +12,7 @@ namespace et {
 __global__ void __launch_bounds__(256) k_pstat(const TestDesc* __restrict__ descs,
                                                const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int64_t col = (blockIdx.x - offs[ti]) * 256 + threadIdx.x;
   if (col >= d.B_pad) return;
   double q = 0.0;
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(256) k_final(const TestDesc* __restrict__ desc
                                                const int64_t* __restrict__ sel, int ntests) {
   __shared__ int64_t cnt[256];
   if (sel && sel[blockIdx.x + 1] == sel[blockIdx.x]) return;
-  const TestDesc& d = descs[blockIdx.x];
+  const TestDesc d = descs[blockIdx.x];
   const int tid = threadIdx.x;
   const double thr = d.pstat[d.B];
   const bool bad = d.flags[0] != 0 || d.flags[2] != 0;
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(256) k_final(const TestDesc* __restrict__ desc
 template <typename T>
 __global__ void __launch_bounds__(256) k_unpack(const TestDesc* __restrict__ descs, T* dxx,
                                                 T* dyy, T* dxy) {
-  const TestDesc& d = descs[0];
+  const TestDesc d = descs[0];
   const int64_t nxx = (int64_t)d.nx * d.nx, nyy = (int64_t)d.ny * d.ny,
                 nxy = (int64_t)d.nx * d.ny;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(256) k_unpack(const TestDesc* __restrict__ des
 // Caller-supplied splits (public layout, words[q * W + t/32]) -> internal layout.
 __global__ void __launch_bounds__(256) k_member_import(const TestDesc* __restrict__ descs,
                                                        const uint32_t* __restrict__ words) {
-  const TestDesc& d = descs[0];
+  const TestDesc d = descs[0];
   const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (col >= d.B_pad) return;
   const int64_t n = (int64_t)d.nx + d.ny, W = (n + 31) / 32;

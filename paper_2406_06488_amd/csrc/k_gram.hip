@@ -50,30 +50,84 @@ __device__ inline float block_value_f32(const TestDesc& d, const TileCtx& c, int
   return d.kind == KIND_ED ? sqrtf(d2) : expf((float)(-d.gamma) * d2);
 }
 
-// Row / column sums of the LDS tile and its coalesced store.
-__device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, float* tl) {
-  __syncthreads();
+// Epilogue through LDS, half a tile (64 rows) at a time so the workgroup needs at most
+// ~36 KB of LDS: the waves holding those rows write their values, then FP64 row sums
+// (complete per half), column sums (accumulated over both halves in row order) and a
+// coalesced store of the half tile.  v[mb][nb][e] holds the block value of row
+// wm*64 + mb*32 + 8*(e/4) + 4*h + e%4, column wn*64 + nb*32 + lane%32.
+constexpr int HALF = TILE / 2;
+__device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, float* tl,
+                                       const f32x16 (&v)[2][2], int wm, int wn, int h, int lr) {
   const int tid = threadIdx.x;
-  double s = 0.0;
-  if (tid < TILE) {
-    for (int k = 0; k < TILE; ++k) s += (double)tl[tid * TILE_LDS + k];
-    d.tsum[(int64_t)c.t * 2 * TILE + tid] = s;
-  } else {
-    const int col = tid - TILE;
-    for (int k = 0; k < TILE; ++k) s += (double)tl[k * TILE_LDS + col];
-    d.tsum[(int64_t)c.t * 2 * TILE + TILE + col] = s;
-  }
   float* D = (float*)d.D + (int64_t)c.t * TILE * TILE;
-  for (int e = tid; e < TILE * TILE; e += 256) D[e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
+  double colsum = 0.0;
+  for (int half = 0; half < 2; ++half) {
+    __syncthreads();
+    if (wm == half) {
+      for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < 2; ++nb)
+          for (int e = 0; e < 16; ++e) {
+            const int r = mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);  // row within the half
+            tl[r * TILE_LDS + wn * 64 + nb * 32 + lr] = v[mb][nb][e];
+          }
+    }
+    __syncthreads();
+    if (tid < HALF) {
+      double s = 0.0;
+      for (int k = 0; k < TILE; ++k) s += (double)tl[tid * TILE_LDS + k];
+      d.tsum[(int64_t)c.t * 2 * TILE + half * HALF + tid] = s;
+    } else if (tid >= TILE) {
+      const int col = tid - TILE;
+      for (int k = 0; k < HALF; ++k) colsum += (double)tl[k * TILE_LDS + col];
+    }
+    for (int e = tid; e < HALF * TILE; e += 256)
+      D[half * HALF * TILE + e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
+  }
+  if (tid >= TILE) d.tsum[(int64_t)c.t * 2 * TILE + TILE + (tid - TILE)] = colsum;
+}
+
+// Gram entries -> block values in place.  d^2 = |w_a|^2 + |w_b|^2 - 2 g; pairs with
+// d^2 < 1e-3 (|w_a|^2 + |w_b|^2), where that difference has cancelled most of its
+// digits, are recomputed as a direct FP32 difference of the input rows.
+__device__ inline void gram_epilogue(const TestDesc& d, const TileCtx& c, f32x16 (&acc)[2][2],
+                                     int wm, int wn, int h, int lr) {
+  __syncthreads();
+  const float* nrm = (const float*)d.nrm;
+  int refined = 0;
+  for (int mb = 0; mb < 2; ++mb)
+    for (int nb = 0; nb < 2; ++nb) {
+      const int col = wn * 64 + nb * 32 + lr;
+      const float nc = nrm[(int64_t)c.j * TILE + col];
+      for (int e = 0; e < 16; ++e) {
+        const int r = wm * 64 + mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+        const float nr = nrm[(int64_t)c.i * TILE + r];
+        float d2 = nr + nc - 2.0f * acc[mb][nb][e];
+        if (d.refine && r < c.rows_i && col < c.rows_j && !(c.diag && r == col) &&
+            d2 < 1e-3f * (nr + nc)) {
+          const float* xa = input_row_f32(d, c.i, r);
+          const float* xb = input_row_f32(d, c.j, col);
+          float s = 0.0f;
+          for (int k = 0; k < d.p; ++k) {
+            const float df = xa[k] - xb[k];
+            s = fmaf(df, df, s);
+          }
+          d2 = s;
+          ++refined;
+        }
+        acc[mb][nb][e] = block_value_f32(d, c, r, col, d2);
+      }
+    }
+  if (refined) atomicAdd(&d.flags[1], refined);
 }
 
 // ---------------------------------------------------------------- FP32 MFMA
 // 4 waves as 2 x 2, each 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x2_f32.
 __global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ offs, int ntests) {
-  __shared__ float smem[TILE * TILE_LDS];
+  __shared__ float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F32 ? HALF * TILE_LDS
+                                                                  : 2 * TILE * LDS_ROW_F32];
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
   const float* Wa = (const float*)d.W + (int64_t)c.i * TILE * d.p_pad;
   const float* Wb = (const float*)d.W + (int64_t)c.j * TILE * d.p_pad;
@@ -113,20 +167,8 @@ __global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ d
                                                                0, 0, 0);
     }
   }
-  __syncthreads();
-  const float* nrm = (const float*)d.nrm;
-  for (int mb = 0; mb < 2; ++mb)
-    for (int nb = 0; nb < 2; ++nb) {
-      const int col = wn * 64 + nb * 32 + lr;
-      const float nc = nrm[(int64_t)c.j * TILE + col];
-      for (int e = 0; e < 16; ++e) {
-        const int r = wm * 64 + mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-        const float nr = nrm[(int64_t)c.i * TILE + r];
-        const float d2 = nr + nc - 2.0f * acc[mb][nb][e];
-        smem[r * TILE_LDS + col] = block_value_f32(d, c, r, col, d2);
-      }
-    }
-  finish_tile_f32(d, c, smem);
+  gram_epilogue(d, c, acc, wm, wn, h, lr);
+  finish_tile_f32(d, c, smem, acc, wm, wn, h, lr);
 }
 
 // ---------------------------------------------------------------- BF16 MFMA
@@ -134,9 +176,10 @@ __global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ d
 // falls below 1e-3 of the norm sum are recomputed from the FP32 input rows.
 __global__ void __launch_bounds__(256) k_gram_bf16(const TestDesc* __restrict__ descs,
                                                    const int64_t* __restrict__ offs, int ntests) {
-  __shared__ float smem[TILE * TILE_LDS];
+  __shared__ float smem[HALF * TILE_LDS > TILE * LDS_ROW_BF16 ? HALF * TILE_LDS
+                                                              : TILE * LDS_ROW_BF16];
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
   const uint16_t* Wa = (const uint16_t*)d.W + (int64_t)c.i * TILE * d.p_pad;
   const uint16_t* Wb = (const uint16_t*)d.W + (int64_t)c.j * TILE * d.p_pad;
@@ -173,34 +216,8 @@ __global__ void __launch_bounds__(256) k_gram_bf16(const TestDesc* __restrict__ 
               __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
     }
   }
-  __syncthreads();
-  const float* nrm = (const float*)d.nrm;
-  int refined = 0;
-  for (int mb = 0; mb < 2; ++mb)
-    for (int nb = 0; nb < 2; ++nb) {
-      const int col = wn * 64 + nb * 32 + lr;
-      const float nc = nrm[(int64_t)c.j * TILE + col];
-      for (int e = 0; e < 16; ++e) {
-        const int r = wm * 64 + mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-        const float nr = nrm[(int64_t)c.i * TILE + r];
-        float d2 = nr + nc - 2.0f * acc[mb][nb][e];
-        if (d.refine && r < c.rows_i && col < c.rows_j && !(c.diag && r == col) &&
-            d2 < 1e-3f * (nr + nc)) {
-          const float* xa = input_row_f32(d, c.i, r);
-          const float* xb = input_row_f32(d, c.j, col);
-          float s = 0.0f;
-          for (int k = 0; k < d.p; ++k) {
-            const float df = xa[k] - xb[k];
-            s = fmaf(df, df, s);
-          }
-          d2 = s;
-          ++refined;
-        }
-        smem[r * TILE_LDS + col] = block_value_f32(d, c, r, col, d2);
-      }
-    }
-  if (refined) atomicAdd(&d.flags[1], refined);
-  finish_tile_f32(d, c, smem);
+  gram_epilogue(d, c, acc, wm, wn, h, lr);
+  finish_tile_f32(d, c, smem, acc, wm, wn, h, lr);
 }
 
 // ---------------------------------------------------------------- FP64 direct
@@ -214,7 +231,7 @@ __global__ void __launch_bounds__(256) k_dist_f64(const TestDesc* __restrict__ d
   __shared__ double rp[TILE * 16];
   __shared__ double cp[16 * TILE];
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
   const double* Wa = (const double*)d.W + (int64_t)c.i * TILE * d.p_pad;
   const double* Wb = (const double*)d.W + (int64_t)c.j * TILE * d.p_pad;

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ des
                                                 const int64_t* __restrict__ offs, int ntests) {
   __shared__ uint32_t V[2][MCH][MSPL];
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int64_t col0 = (blockIdx.x - offs[ti]) * MSPL;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n = (int64_t)d.nx + d.ny;
@@ -124,37 +124,45 @@ __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ des
   };
   draw_chunk(0, 0, tid, 256);
   __syncthreads();
+  // Selection scan.  Because v_t <= n - t - 1, the test v_t < need already keeps
+  // every remaining item once need == n - t and none once need == 0.
   const int64_t b = col0 + lane;
   const bool drawn = b < d.B;
-  int64_t need = d.nx, wcur = -1;
+  const int nx = d.nx, ntot = (int)n;
+  const int64_t BP = d.B_pad;
+  uint32_t need = (uint32_t)nx;
   uint32_t word = 0;
   for (int ch = 0; ch < nch; ++ch) {
     if (wave != 0) {
       if (ch + 1 < nch) draw_chunk(ch + 1, (ch + 1) & 1, tid - 64, 192);
     } else if (drawn) {
-      const int64_t t0 = (int64_t)ch * MCH;
-      for (int k = 0; k < MCH; ++k) {
-        const int64_t t = t0 + k;
-        if (t >= n) break;
-        const int64_t m = n - t;
-        uint32_t take;
-        if (need == 0) take = 0;
-        else if (need == m) take = 1;
-        else take = (int64_t)V[ch & 1][k][lane] < need ? 1u : 0u;
-        need -= take;
-        const int64_t pos = t < d.nx ? t : ybase + (t - d.nx);
-        const int64_t w = pos >> 5;
-        if (w != wcur) {
-          if (wcur >= 0) Z[wcur * d.B_pad + b] = word;
-          word = 0;
-          wcur = w;
+      const int t0 = ch * MCH;
+      const int kend = min(MCH, ntot - t0);
+#pragma unroll
+      for (int k8 = 0; k8 < MCH; k8 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = V[ch & 1][k8 + e][lane];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = k8 + e;
+          if (k < kend) {
+            const int t = t0 + k;
+            const uint32_t take = v[e] < need ? 1u : 0u;
+            need -= take;
+            const int pos = t < nx ? t : (int)ybase + (t - nx);
+            word |= take << (pos & 31);
+            // flush at the end of a word or of the X / Y part
+            if ((pos & 31) == 31 || t == nx - 1 || t == ntot - 1) {
+              Z[(int64_t)(pos >> 5) * BP + b] = word;
+              word = 0;
+            }
+          }
         }
-        word |= take << (pos & 31);
       }
     }
     __syncthreads();
   }
-  if (wave == 0 && drawn && wcur >= 0) Z[wcur * d.B_pad + b] = word;
 }
 
 // Public layout: words[(b - b0) * W + t / 32], bit t % 32, W = ceil(n / 32).

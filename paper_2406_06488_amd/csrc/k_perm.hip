@@ -24,14 +24,13 @@ namespace et {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-__device__ inline uint32_t two_bits_bf16(uint32_t b) {
-  // bit 0 -> low bf16 (1.0 = 0x3F80), bit 1 -> high bf16
-  return ((b & 1u) * 0x3F80u) | (((b >> 1) & 1u) * 0x3F800000u);
-}
-
+// 8 membership bits -> 8 bf16 values 0.0 / 1.0 (element k = bit k).  m = byte * 0x8001
+// holds bit k at positions k and k + 15, so (m >> 2q) & 0x10001 puts bits 2q and 2q+1
+// at positions 0 and 16; times 0x3F80 (bf16 1.0) that is the packed pair.
 __device__ inline bf16x8 expand_byte(uint32_t byte) {
-  const uint4 u = make_uint4(two_bits_bf16(byte), two_bits_bf16(byte >> 2),
-                             two_bits_bf16(byte >> 4), two_bits_bf16(byte >> 6));
+  const uint32_t m = byte * 0x8001u;
+  const uint4 u = make_uint4((m & 0x10001u) * 0x3F80u, ((m >> 2) & 0x10001u) * 0x3F80u,
+                             ((m >> 4) & 0x10001u) * 0x3F80u, ((m >> 6) & 0x10001u) * 0x3F80u);
   return __builtin_bit_cast(bf16x8, u);
 }
 
@@ -54,74 +53,120 @@ __device__ inline PermUnit perm_unit(const TestDesc& d, int ti, int64_t local,
   return u;
 }
 
+// Workgroup: 8 waves over two chunks of 256 split columns; wave w owns columns
+// (w & 3) * 64 .. + 63 of chunk w >> 2 and all 128 rows of the row tile (4 row blocks x 2
+// column blocks of 32 x 32 accumulators).  The A tile (i, j) -- S bf16 planes in
+// fragment order -- and the membership words of column tile j stream straight into one
+// of two LDS buffers (global_load_lds) while the other buffer is multiplied.  Each wave
+// folds the row weights of its own columns at the end: no cross-wave reduction.
+constexpr int PERM_THREADS = 512;
+
+__device__ inline void load_to_lds16(const void* g, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave_base, 16,
+                                   0, 0);
+}
+
 template <int S>
-__global__ void __launch_bounds__(256) k_perm_mfma(const TestDesc* __restrict__ descs,
-                                                   const int64_t* __restrict__ offs, int ntests,
-                                                   const int32_t* __restrict__ pcr) {
-  __shared__ double qs[4][MAX_CC][NP];  // per-wave FP64 column sums
+__global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __restrict__ descs,
+                                                            const int64_t* __restrict__ offs,
+                                                            int ntests,
+                                                            const int32_t* __restrict__ pcr) {
+  constexpr int FR = TILE * TILE / 8;         // 16-byte fragments per plane (2048)
+  constexpr int ZW = TILE_WORDS * 2 * NP / 4;  // 16-byte groups of membership words (512)
+  constexpr int BUF = S * FR + ZW;            // 16-byte slots per buffer
+  __shared__ uint4 lds[2 * BUF];
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const PermUnit u = perm_unit(d, ti, blockIdx.x - offs[ti], pcr);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, lr = lane & 31;
-  const int ncc = u.ce - u.cb;
-  for (int e = lane; e < ncc * NP; e += 64) qs[w][e / NP][e % NP] = 0.0;
-  const uint16_t* planes = (const uint16_t*)d.planes;
-  const uint32_t* Z = d.Z;
   const int64_t BP = d.B_pad;
+  const int nch = u.ce - u.cb;  // 1 or 2
+  const int cw = w >> 2;        // this wave's chunk
+  const bool active = cw < nch;
+  const uint4* planes = (const uint4*)d.planes;
+  const uint32_t* Z = d.Z;
+  const int lcol = cw * NP + (w & 3) * 64 + lr;  // column within the workgroup's 512 (nb = 0)
 
+  // Queue the A tile and membership words of column tile j into buffer `buf`.
+  auto issue = [&](int j, int buf) {
+    uint4* dst = lds + buf * BUF;
+    const uint4* src = planes + (int64_t)tile_index(u.i, j, d.nt) * S * FR;
+#pragma unroll
+    for (int r = 0; r < S * FR / PERM_THREADS; ++r) {
+      const int q = tid + PERM_THREADS * r;
+      load_to_lds16(src + q, dst + (q - lane));
+    }
+    // words (j*4 + q) of the 512 columns: 128 lanes x 16 bytes per word row q
+    const int q = tid >> 7, part = tid & 127;
+    if (part * 4 < nch * NP) {
+      const uint32_t* zsrc =
+          Z + (int64_t)(j * TILE_WORDS + q) * BP + (int64_t)u.cb * NP + part * 4;
+      load_to_lds16(zsrc, dst + S * FR + (tid - lane));
+    }
+  };
+
+  f32x16 acc[4][2];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[mb][nb][e] = 0.0f;
+
+  issue(u.j0, 0);
   for (int j = u.j0; j < u.j1; ++j) {
-    const int t = tile_index(u.i, j, d.nt);
-    bf16x8 a[8][S];
-    const uint16_t* At = planes + (int64_t)t * S * TILE * TILE + ((int64_t)(w * 8) * 64 + lane) * 8;
+    const int buf = (j - u.j0) & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads into `buf` have landed
+    __syncthreads();                // everyone's have, and `buf ^ 1` is free again
+    if (j + 1 < u.j1) issue(j + 1, buf ^ 1);
+    const uint4* A = lds + buf * BUF;
+    const uint32_t* zl = (const uint32_t*)(A + S * FR);  // [q][512 columns]
+    if (active) {
+      uint32_t zw[2][TILE_WORDS];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks)
+      for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-      for (int s = 0; s < S; ++s) a[ks][s] = *(const bf16x8*)(At + s * TILE * TILE + ks * 512);
-    for (int c = u.cb; c < u.ce; ++c) {
-      // membership words of column tile j (4 words = 128 items) for split c*NP + nb*32 + lr
-      const uint32_t* Zc = Z + (int64_t)(j * TILE_WORDS) * BP + (int64_t)c * NP + lr;
-      uint32_t zw[8][TILE_WORDS];
+        for (int q = 0; q < TILE_WORDS; ++q) zw[nb][q] = zl[q * 2 * NP + lcol + nb * 32];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
+      for (int ks = 0; ks < 8; ++ks) {
+        bf16x8 a[4][S];
 #pragma unroll
-        for (int q = 0; q < TILE_WORDS; ++q) zw[nb][q] = Zc[(int64_t)q * BP + nb * 32];
-      // row bits of this wave's 32 rows of tile i
-      uint32_t zr[8];
-      const uint32_t* Zr = Z + (int64_t)(u.i * TILE_WORDS + w) * BP + (int64_t)c * NP + lr;
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb) zr[nb] = Zr[nb * 32];
-      f32x16 acc[8];
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[nb][e] = 0.0f;
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-          const bf16x8 b = expand_byte((zw[nb][ks >> 1] >> ((ks & 1) * 16 + h * 8)) & 0xFFu);
+        for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
           for (int s = 0; s < S; ++s)
-            acc[nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks][s], b, acc[nb], 0, 0, 0);
-        }
-      // fold the row weights: sum over this wave's rows a of z_c[a] * U[a, c]
+            a[mb][s] = __builtin_bit_cast(bf16x8, A[s * FR + (mb * 8 + ks) * 64 + lane]);
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) {
-        double q = 0.0;
+        for (int nb = 0; nb < 2; ++nb) {
+          const bf16x8 b = expand_byte((zw[nb][ks >> 1] >> ((ks & 1) * 16 + h * 8)) & 0xFFu);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int bit = 8 * (e >> 2) + 4 * h + (e & 3);
-          if ((zr[nb] >> bit) & 1u) q += (double)acc[nb][e];
+          for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+              acc[mb][nb] =
+                  __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb][s], b, acc[mb][nb], 0, 0, 0);
         }
-        q += __shfl_xor(q, 32, 64);
-        if (h == 0) qs[w][c - u.cb][nb * 32 + lr] += q;
       }
     }
   }
-  __syncthreads();
-  for (int c = 0; c < ncc; ++c) {
-    const double s = ((qs[0][c][tid] + qs[1][c][tid]) + qs[2][c][tid]) + qs[3][c][tid];
-    d.part[(int64_t)u.rk * BP + (int64_t)(u.cb + c) * NP + tid] = s;
+  if (!active) return;
+  // fold the row weights: q_c = sum over the tile's rows a of z_c[a] * U[a, c]
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const int64_t col = (int64_t)u.cb * NP + lcol + nb * 32;
+    double q = 0.0;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const uint32_t wz = Z[(int64_t)(u.i * TILE_WORDS + mb) * BP + col];
+      float f = 0.0f;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int bit = 8 * (e >> 2) + 4 * h + (e & 3);
+        f += ((wz >> bit) & 1u) ? acc[mb][nb][e] : 0.0f;
+      }
+      q += (double)f;
+    }
+    q += __shfl_xor(q, 32, 64);
+    if (h == 0) d.part[(int64_t)u.rk * BP + col] = q;
   }
 }
 
@@ -131,7 +176,7 @@ __global__ void __launch_bounds__(256) k_perm_f64(const TestDesc* __restrict__ d
                                                   const int32_t* __restrict__ pcr) {
   __shared__ double Ts[32 * TILE];
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const PermUnit u = perm_unit(d, ti, blockIdx.x - offs[ti], pcr);
   const int tid = threadIdx.x;
   const uint32_t* Z = d.Z;
@@ -170,9 +215,8 @@ void launch_perm(int variant, int64_t blocks, hipStream_t st, const TestDesc* d,
   const dim3 g((unsigned)blocks), b(256);
   switch (variant) {
     case 0: hipLaunchKernelGGL(k_perm_f64, g, b, 0, st, d, offs, ntests, pcr); break;
-    case 1: hipLaunchKernelGGL(k_perm_mfma<1>, g, b, 0, st, d, offs, ntests, pcr); break;
-    case 2: hipLaunchKernelGGL(k_perm_mfma<2>, g, b, 0, st, d, offs, ntests, pcr); break;
-    default: hipLaunchKernelGGL(k_perm_mfma<3>, g, b, 0, st, d, offs, ntests, pcr); break;
+    case 1: hipLaunchKernelGGL(k_perm_mfma<1>, g, dim3(PERM_THREADS), 0, st, d, offs, ntests, pcr); break;
+    default: hipLaunchKernelGGL(k_perm_mfma<2>, g, dim3(PERM_THREADS), 0, st, d, offs, ntests, pcr); break;
   }
 }
 

@@ -22,7 +22,7 @@ __device__ inline double load_in_f64(const TestDesc& d, int64_t t, int k) {
 __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int64_t local = blockIdx.x - offs[ti];
   const int ncb = (d.p + 255) / 256;
   const int rc = (int)(local / ncb);
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
 __global__ void __launch_bounds__(256) k_colmean(const TestDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int k = (int)(blockIdx.x - offs[ti]) * 256 + threadIdx.x;
   if (k >= d.p) return;
   double s = 0.0;
@@ -56,7 +56,7 @@ __device__ inline double wave_sum(double v) {
 __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ descs,
                                                const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int64_t local = blockIdx.x - offs[ti];
   const int lane = threadIdx.x & 63;
   const int64_t pos = local * 4 + (threadIdx.x >> 6);

@@ -13,7 +13,7 @@ namespace et {
 __global__ void __launch_bounds__(256) k_rowsum(const TestDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc& d = descs[ti];
+  const TestDesc d = descs[ti];
   const int64_t pos = (blockIdx.x - offs[ti]) * 256 + threadIdx.x;
   const int64_t npad = (int64_t)d.nt * TILE;
   if (pos >= npad) return;
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
                                                   const int64_t* __restrict__ sel, int ntests) {
   __shared__ double red[3][256][2];
   if (sel && sel[blockIdx.x + 1] == sel[blockIdx.x]) return;
-  const TestDesc& d = descs[blockIdx.x];
+  const TestDesc d = descs[blockIdx.x];
   const int tid = threadIdx.x;
   Neu sxx{0, 0}, syy{0, 0}, sxy{0, 0};
   const int64_t xend = (int64_t)d.tx * TILE, npad = (int64_t)d.nt * TILE;

@@ -70,8 +70,12 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.ty = (int32_t)((r.ny + TILE - 1) / TILE);
   d.nt = d.tx + d.ty;
   d.ntiles = d.nt * (d.nt + 1) / 2;
-  d.splits = r.prec == ETEST_PREC_F32 ? 3
-             : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 3) : 1;
+  // bf16 planes of the centred blocks: hi + lo keeps 16 significant bits, an error of
+  // at most 2^-17 of each centred entry (the FP32 blocks themselves carry ~2^-24 of the
+  // uncentred entry, which is of the same absolute size); one plane for the BF16 form
+  // would keep 8 bits.
+  d.splits = r.prec == ETEST_PREC_F32 ? 2
+             : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 2) : 1;
   d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
   d.kc = (int32_t)(kc_override > 0 ? kc_override : 8);
   int nrk = 0;
@@ -81,7 +85,10 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.nrowchunks = (int32_t)((n + 127) / 128);
   d.B = r.B;
   d.B_pad = (r.B + 1 + NP - 1) / NP * NP;
-  d.cc = (int32_t)std::min<int64_t>(env_int("ETEST_CC", 4, 1, MAX_CC), d.B_pad / NP);
+  // split chunks per resampling workgroup: the MFMA kernel holds two accumulator sets
+  const int cc_max = r.prec == ETEST_PREC_F64 ? MAX_CC : 2;
+  d.cc = (int32_t)std::min<int64_t>(std::min(env_int("ETEST_CC", cc_max, 1, MAX_CC), cc_max),
+                                    d.B_pad / NP);
   d.seed = r.seed;
   d.gamma = r.kind == ETEST_MMD ? r.gamma : 0.0;
   d.X = r.X;
