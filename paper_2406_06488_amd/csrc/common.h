@@ -53,8 +53,10 @@ struct TestDesc {
   void* nrm;
   void* D;
   double* tsum;
+  float* tmax;       // [ntiles] largest |entry| of each stored tile
   double* rsum;
-  double* obs;       // [0..2] S_XX, S_YY, S_XY; [3] observed statistic; [4] R
+  double* obs;       // [0..2] S_XX, S_YY, S_XY; [3] observed statistic; [4] R;
+                     // [5] power-of-two scale of the fp16 planes
   void* planes;
   uint32_t* Z;
   double* part;

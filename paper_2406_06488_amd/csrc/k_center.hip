@@ -10,11 +10,13 @@
 // a single quadratic form over the three stored blocks.  Diagonal tiles are
 // halved, so that z^T Dc z = 2 * sum over stored tiles (i <= j) of z_i^T T_ij z_j.
 //
-// FP32/BF16 forms: the centred value, rounded to FP32, is split into S bf16
-// planes hi + mid + lo (S = 3 represents the FP32 value exactly) laid out in
-// v_mfma_f32_32x32x16_bf16 A-fragment order: fragment (mb, ks) of a tile is 64
-// lanes x 8 bf16, lane = row%32 + 32 * ((col%16)/8), for rows 32 mb.. and
-// columns 16 ks.. .  FP64 form: one FP64 row-major tile.
+// FP32/BF16 forms: the centred value, scaled by the test's power of two 2^e (so every
+// value fits fp16), becomes two fp16 planes hi = fp16(v) and lo = fp16((v - hi) 2^11);
+// the resampling stage multiplies lo by split bits worth 2^-11, so hi + lo 2^-11 holds
+// v to about 2^-22 of itself with both products exact.  Planes are laid out in
+// v_mfma_f32_32x32x16_f16 A-fragment order: fragment (mb, ks) of a tile is 64 lanes x
+// 8 values, lane = row%32 + 32 * ((col%16)/8), for rows 32 mb.. and columns 16 ks.. .
+// FP64 form: one FP64 row-major tile.
 #include "common.h"
 
 namespace et {
@@ -30,6 +32,10 @@ __device__ inline double center_value(const TestDesc& d, int i, int j, int r, in
   return x;
 }
 
+__device__ inline uint32_t pack_h2(_Float16 a, _Float16 b) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
 __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict__ descs,
                                                       const int64_t* __restrict__ offs,
                                                       int ntests) {
@@ -42,36 +48,28 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
   const double n = (double)d.nx + (double)d.ny;
   const double inv_n = 1.0 / n;
   const double c0 = d.obs[4] / (n * n);
+  const double scale = d.obs[5];
   const int S = d.splits;
   const float* Dt = (const float*)d.D + (int64_t)t * TILE * TILE;
   uint16_t* P = (uint16_t*)d.planes + (int64_t)t * S * TILE * TILE;
   for (int q = threadIdx.x; q < TILE * TILE / 8; q += 256) {
     const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
     const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
-    uint16_t hi[8], mid[8], lo[8];
+    _Float16 hi[8], lo[8];
     for (int e = 0; e < 8; ++e) {
       const double x = center_value(d, i, j, r, c0l + e, rows_i, rows_j,
-                                    (double)Dt[r * TILE + c0l + e], inv_n, c0);
-      const float v = (float)x;
-      hi[e] = f32_to_bf16_rn(v);
-      const float r1 = v - bf16_to_f32(hi[e]);
-      mid[e] = f32_to_bf16_rn(r1);
-      const float r2 = r1 - bf16_to_f32(mid[e]);
-      lo[e] = f32_to_bf16_rn(r2);
+                                    (double)Dt[r * TILE + c0l + e], inv_n, c0) * scale;
+      hi[e] = (_Float16)x;
+      lo[e] = (_Float16)((x - (double)hi[e]) * 2048.0);
     }
     uint4 w;
-    w.x = hi[0] | ((uint32_t)hi[1] << 16); w.y = hi[2] | ((uint32_t)hi[3] << 16);
-    w.z = hi[4] | ((uint32_t)hi[5] << 16); w.w = hi[6] | ((uint32_t)hi[7] << 16);
+    w.x = pack_h2(hi[0], hi[1]); w.y = pack_h2(hi[2], hi[3]);
+    w.z = pack_h2(hi[4], hi[5]); w.w = pack_h2(hi[6], hi[7]);
     *(uint4*)(P + (int64_t)q * 8) = w;
     if (S > 1) {
-      w.x = mid[0] | ((uint32_t)mid[1] << 16); w.y = mid[2] | ((uint32_t)mid[3] << 16);
-      w.z = mid[4] | ((uint32_t)mid[5] << 16); w.w = mid[6] | ((uint32_t)mid[7] << 16);
+      w.x = pack_h2(lo[0], lo[1]); w.y = pack_h2(lo[2], lo[3]);
+      w.z = pack_h2(lo[4], lo[5]); w.w = pack_h2(lo[6], lo[7]);
       *(uint4*)(P + TILE * TILE + (int64_t)q * 8) = w;
-    }
-    if (S > 2) {
-      w.x = lo[0] | ((uint32_t)lo[1] << 16); w.y = lo[2] | ((uint32_t)lo[3] << 16);
-      w.z = lo[4] | ((uint32_t)lo[5] << 16); w.w = lo[6] | ((uint32_t)lo[7] << 16);
-      *(uint4*)(P + 2 * TILE * TILE + (int64_t)q * 8) = w;
     }
   }
 }

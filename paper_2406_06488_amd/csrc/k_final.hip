@@ -17,6 +17,7 @@ __global__ void __launch_bounds__(256) k_pstat(const TestDesc* __restrict__ desc
   if (col >= d.B_pad) return;
   double q = 0.0;
   for (int rk = 0; rk < d.n_rowk; ++rk) q += d.part[(int64_t)rk * d.B_pad + col];
+  if (d.prec != PREC_F64) q /= d.obs[5];  // undo the power-of-two scale of the fp16 planes
   const double a = 1.0 / d.nx + 1.0 / d.ny;
   const double coef = a * a * 2.0;
   d.pstat[col] = d.kind == KIND_ED ? -coef * q : coef * q;

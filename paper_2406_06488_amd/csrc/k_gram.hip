@@ -58,9 +58,12 @@ __device__ inline float block_value_f32(const TestDesc& d, const TileCtx& c, int
 constexpr int HALF = TILE / 2;
 __device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, float* tl,
                                        const f32x16 (&v)[2][2], int wm, int wn, int h, int lr) {
+  __shared__ unsigned int tile_max_bits;
   const int tid = threadIdx.x;
   float* D = (float*)d.D + (int64_t)c.t * TILE * TILE;
   double colsum = 0.0;
+  float vmax = 0.0f;
+  if (tid == 0) tile_max_bits = 0u;
   for (int half = 0; half < 2; ++half) {
     __syncthreads();
     if (wm == half) {
@@ -74,7 +77,11 @@ __device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, floa
     __syncthreads();
     if (tid < HALF) {
       double s = 0.0;
-      for (int k = 0; k < TILE; ++k) s += (double)tl[tid * TILE_LDS + k];
+      for (int k = 0; k < TILE; ++k) {
+        const float x = tl[tid * TILE_LDS + k];
+        s += (double)x;
+        vmax = fmaxf(vmax, fabsf(x));
+      }
       d.tsum[(int64_t)c.t * 2 * TILE + half * HALF + tid] = s;
     } else if (tid >= TILE) {
       const int col = tid - TILE;
@@ -84,6 +91,10 @@ __device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, floa
       D[half * HALF * TILE + e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
   }
   if (tid >= TILE) d.tsum[(int64_t)c.t * 2 * TILE + TILE + (tid - TILE)] = colsum;
+  // non-negative floats order like their bit patterns
+  if (tid < HALF) atomicMax(&tile_max_bits, __float_as_uint(vmax));
+  __syncthreads();
+  if (tid == 0) d.tmax[c.t] = __uint_as_float(tile_max_bits);
 }
 
 // Gram entries -> block values in place.  d^2 = |w_a|^2 + |w_b|^2 - 2 g; pairs with

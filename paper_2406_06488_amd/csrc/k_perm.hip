@@ -9,29 +9,32 @@
 // tiles make z^T Dc z = 2 * sum over stored tiles (i <= j) of z_i^T T_ij z_j.
 //
 // Work unit: (row tile i, column tiles [j0, j1), split-column chunks [cb, ce)),
-// chunk = NP = 256 splits.  FP32 / BF16 forms: wave w owns rows 32w..32w+31 of
-// the row tile; the A fragments of its rows of tile (i, j) -- S bf16 planes whose
-// sum is the centred FP32 value (S = 3 exact) -- are loaded once into registers
-// and reused for every chunk; membership bits expand in registers to exact 0/1
-// bf16 B fragments, so the products on v_mfma_f32_32x32x16_bf16 are exact.  Each
-// (tile, chunk) product is folded into per-wave FP64 column sums in LDS; the
-// four waves are added in a fixed order at the end.  FP64 form: the same
-// quadratic form on the FP64 vector ALU, one thread per split.
+// chunk = NP = 256 splits.  FP32 / BF16 forms: the centred tiles are held as two fp16
+// planes (value = hi + lo 2^-11, see k_center.hip); membership bits expand to exact
+// fp16 B fragments worth 1 (for hi) and 2^-11 (for lo), so every product on
+// v_mfma_f32_32x32x16_f16 is exact and only the FP32 accumulation order differs from
+// an exact evaluation; partial sums per row range are reduced in FP64.  FP64 form:
+// the same quadratic form on the FP64 vector ALU, one thread per split.
 #include "common.h"
 
 namespace et {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// 8 membership bits -> 8 bf16 values 0.0 / 1.0 (element k = bit k).  m = byte * 0x8001
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// 8 membership bits -> 8 fp16 values 0.0 / 1.0 (element k = bit k).  m = byte * 0x8001
 // holds bit k at positions k and k + 15, so (m >> 2q) & 0x10001 puts bits 2q and 2q+1
-// at positions 0 and 16; times 0x3F80 (bf16 1.0) that is the packed pair.
-__device__ inline bf16x8 expand_byte(uint32_t byte) {
+// at positions 0 and 16; times 0x3C00 (fp16 1.0) that is the packed pair.
+__device__ inline uint4 expand_byte(uint32_t byte) {
   const uint32_t m = byte * 0x8001u;
-  const uint4 u = make_uint4((m & 0x10001u) * 0x3F80u, ((m >> 2) & 0x10001u) * 0x3F80u,
-                             ((m >> 4) & 0x10001u) * 0x3F80u, ((m >> 6) & 0x10001u) * 0x3F80u);
-  return __builtin_bit_cast(bf16x8, u);
+  return make_uint4((m & 0x10001u) * 0x3C00u, ((m >> 2) & 0x10001u) * 0x3C00u,
+                    ((m >> 4) & 0x10001u) * 0x3C00u, ((m >> 6) & 0x10001u) * 0x3C00u);
+}
+// The same bits worth 2^-11 (fp16 0x1000) for the low plane: 0x3C00 & 0x1000 = 0x1000.
+__device__ inline uint4 low_weights(uint4 u) {
+  return make_uint4(u.x & 0x10001000u, u.y & 0x10001000u, u.z & 0x10001000u, u.w & 0x10001000u);
 }
 
 struct PermUnit {
@@ -55,7 +58,7 @@ __device__ inline PermUnit perm_unit(const TestDesc& d, int ti, int64_t local,
 
 // Workgroup: 8 waves over two chunks of 256 split columns; wave w owns columns
 // (w & 3) * 64 .. + 63 of chunk w >> 2 and all 128 rows of the row tile (4 row blocks x 2
-// column blocks of 32 x 32 accumulators).  The A tile (i, j) -- S bf16 planes in
+// column blocks of 32 x 32 accumulators).  The A tile (i, j) -- S fp16 planes in
 // fragment order -- and the membership words of column tile j stream straight into one
 // of two LDS buffers (global_load_lds) while the other buffer is multiplied.  Each wave
 // folds the row weights of its own columns at the end: no cross-wave reduction.
@@ -129,21 +132,24 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
         for (int q = 0; q < TILE_WORDS; ++q) zw[nb][q] = zl[q * 2 * NP + lcol + nb * 32];
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
-        bf16x8 a[4][S];
+        f16x8 a[4][S];
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
           for (int s = 0; s < S; ++s)
-            a[mb][s] = __builtin_bit_cast(bf16x8, A[s * FR + (mb * 8 + ks) * 64 + lane]);
+            a[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8 + ks) * 64 + lane]);
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-          const bf16x8 b = expand_byte((zw[nb][ks >> 1] >> ((ks & 1) * 16 + h * 8)) & 0xFFu);
+          const uint4 bu = expand_byte((zw[nb][ks >> 1] >> ((ks & 1) * 16 + h * 8)) & 0xFFu);
+          const f16x8 b1 = __builtin_bit_cast(f16x8, bu);
+          const f16x8 b2 = __builtin_bit_cast(f16x8, low_weights(bu));
 #pragma unroll
-          for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-            for (int s = 0; s < S; ++s)
+          for (int mb = 0; mb < 4; ++mb) {
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][0], b1, acc[mb][nb], 0, 0, 0);
+            if (S > 1)
               acc[mb][nb] =
-                  __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb][s], b, acc[mb][nb], 0, 0, 0);
+                  __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][S - 1], b2, acc[mb][nb], 0, 0, 0);
+          }
         }
       }
     }

@@ -84,6 +84,27 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
     d.obs[3] = d.kind == KIND_ED ? (txy - txx) - tyy : (txx + tyy) - txy;
     d.obs[4] = d.obs[0] + d.obs[1] + 2.0 * d.obs[2];  // R = sum of all pooled row sums
   }
+  // Scale of the fp16 planes of the FP32 / BF16 forms: a centred entry
+  // D - c_a - c_b + c0 (all of them within [0, max D] for distances and kernel values)
+  // is at most 4 max|D| in size; scaling by 2^e with 4 max|D| 2^e <= 2^14 keeps every
+  // plane value inside the fp16 range.
+  __shared__ float mx[256];
+  float m = 0.0f;
+  if (d.prec != PREC_F64)
+    for (int t = tid; t < d.ntiles; t += 256) m = fmaxf(m, d.tmax[t]);
+  mx[tid] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) mx[tid] = fmaxf(mx[tid], mx[tid + s]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double bound = 4.0 * (double)mx[0];
+    int e = 0;
+    if (bound > 0.0) e = 14 - (int)ceil(log2(bound));
+    e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    d.obs[5] = ldexp(1.0, e);
+  }
 }
 
 void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {

@@ -106,6 +106,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   sz[B_NRM] = (size_t)npad * (f64 ? 8 : 4);
   sz[B_D] = (size_t)d.ntiles * TILE * TILE * el_d;
   sz[B_TSUM] = (size_t)d.ntiles * 2 * TILE * 8;
+  sz[B_TMAX] = (size_t)d.ntiles * 4;
   sz[B_RSUM] = (size_t)npad * 2 * 8;
   sz[B_OBS] = 8 * 8;
   sz[B_PLANES] = f64 ? (size_t)d.ntiles * TILE * TILE * 8
@@ -171,6 +172,7 @@ void assign_pointers(TestPlan& P, char* r, DevResult* result) {
   d.nrm = r + P.off[B_NRM];
   d.D = r + P.off[B_D];
   d.tsum = (double*)(r + P.off[B_TSUM]);
+  d.tmax = (float*)(r + P.off[B_TMAX]);
   d.rsum = (double*)(r + P.off[B_RSUM]);
   d.obs = (double*)(r + P.off[B_OBS]);
   d.planes = r + P.off[B_PLANES];

@@ -45,8 +45,8 @@ enum Slot {
 };
 
 // Buffer ids inside one test's region.
-enum Buf { B_COLPART, B_COLMEAN, B_W, B_NRM, B_D, B_TSUM, B_RSUM, B_OBS, B_PLANES, B_Z, B_PART,
-           B_PSTAT, B_FLAGS, B_RESULT, B_PERMOUT, B_NBUF };
+enum Buf { B_COLPART, B_COLMEAN, B_W, B_NRM, B_D, B_TSUM, B_TMAX, B_RSUM, B_OBS, B_PLANES, B_Z,
+           B_PART, B_PSTAT, B_FLAGS, B_RESULT, B_PERMOUT, B_NBUF };
 
 struct TestPlan {
   TestDesc d{};              // sizes now, pointers once the workspace is placed
