@@ -9,8 +9,9 @@
 //                           tiles, every XY tile, YY upper tiles -- never a YX tile
 //   tsum   [ntiles][2][T]   FP64 row / column sums of each stored tile
 //   rsum   [n_pad][2]       pooled row sums: same-sample part, cross-sample part
-//   planes [ntiles][S][T*T] double-centred tiles split into S bf16 planes in MFMA
-//                           A-fragment order (FP64 form: one FP64 row-major tile)
+//   planes [ntiles][S][T*T] double-centred tiles, scaled by a power of two and split
+//                           into fp16 planes (hi, lo * 2^11) in MFMA A-fragment
+//                           order (FP64 form: one FP64 row-major tile)
 //   Z      [n_pad/32][B_pad] split membership bits, word w of column c holds items
 //                           32w..32w+31; columns 0..B-1 drawn splits, column B the
 //                           identity split, the rest zero
@@ -26,6 +27,7 @@ constexpr int TILE = 128;            // edge of a stored block tile
 constexpr int TILE_WORDS = TILE / 32;
 constexpr int NP = 256;              // split columns per resampling chunk
 constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
+constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
 enum { KIND_ED = 0, KIND_MMD = 1 };

@@ -133,7 +133,10 @@ __device__ inline void gram_epilogue(const TestDesc& d, const TileCtx& c, f32x16
 
 // ---------------------------------------------------------------- FP32 MFMA
 // 4 waves as 2 x 2, each 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x2_f32.
-__global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ descs,
+// Three resident workgroups per CU (register budget <= 168 per lane): 768 slots, so a
+// 2000 + 2000 test's 528 tiles run in a single round.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gram_f32(const TestDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ offs, int ntests) {
   __shared__ float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F32 ? HALF * TILE_LDS
                                                                   : 2 * TILE * LDS_ROW_F32];
@@ -151,17 +154,43 @@ __global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ d
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
+  // the next 32-wide slice is loaded into registers while the current one is multiplied
+  // 1024 float4 per operand and slice: thread tid owns rows (tid >> 3) + 32 s, column
+  // group (tid & 7); the next slice is loaded into registers while the current one is
+  // multiplied.
+  const int lrow = tid >> 3, lc4 = (tid & 7) * 4;
+  const float* ga = Wa + (int64_t)lrow * d.p_pad + lc4;
+  const float* gb = Wb + (int64_t)lrow * d.p_pad + lc4;
+  const int64_t rstep = (int64_t)32 * d.p_pad;
+  float4 pa0 = *(const float4*)(ga), pa1 = *(const float4*)(ga + rstep);
+  float4 pa2 = *(const float4*)(ga + 2 * rstep), pa3 = *(const float4*)(ga + 3 * rstep);
+  float4 pb0 = *(const float4*)(gb), pb1 = *(const float4*)(gb + rstep);
+  float4 pb2 = *(const float4*)(gb + 2 * rstep), pb3 = *(const float4*)(gb + 3 * rstep);
   for (int k0 = 0; k0 < d.p_pad; k0 += 32) {
     __syncthreads();
-    for (int s = 0; s < 4; ++s) {
-      const int q = tid + 256 * s;  // 1024 float4 per operand
-      const int row = q >> 3, c4 = (q & 7) * 4;
-      const float4 va = *(const float4*)(Wa + (int64_t)row * d.p_pad + k0 + c4);
-      const float4 vb = *(const float4*)(Wb + (int64_t)row * d.p_pad + k0 + c4);
-      *(float4*)(As + row * LDS_ROW_F32 + c4) = va;
-      *(float4*)(Bs + row * LDS_ROW_F32 + c4) = vb;
-    }
+    float* la = As + lrow * LDS_ROW_F32 + lc4;
+    float* lb = Bs + lrow * LDS_ROW_F32 + lc4;
+    *(float4*)(la) = pa0;
+    *(float4*)(la + 32 * LDS_ROW_F32) = pa1;
+    *(float4*)(la + 64 * LDS_ROW_F32) = pa2;
+    *(float4*)(la + 96 * LDS_ROW_F32) = pa3;
+    *(float4*)(lb) = pb0;
+    *(float4*)(lb + 32 * LDS_ROW_F32) = pb1;
+    *(float4*)(lb + 64 * LDS_ROW_F32) = pb2;
+    *(float4*)(lb + 96 * LDS_ROW_F32) = pb3;
     __syncthreads();
+    if (k0 + 32 < d.p_pad) {
+      const float* na = ga + k0 + 32;
+      const float* nb2 = gb + k0 + 32;
+      pa0 = *(const float4*)(na);
+      pa1 = *(const float4*)(na + rstep);
+      pa2 = *(const float4*)(na + 2 * rstep);
+      pa3 = *(const float4*)(na + 3 * rstep);
+      pb0 = *(const float4*)(nb2);
+      pb1 = *(const float4*)(nb2 + rstep);
+      pb2 = *(const float4*)(nb2 + 2 * rstep);
+      pb3 = *(const float4*)(nb2 + 3 * rstep);
+    }
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       // lane half h supplies staged columns 16h .. 16h+15 (the same for A and B)
@@ -185,7 +214,8 @@ __global__ void __launch_bounds__(256) k_gram_f32(const TestDesc* __restrict__ d
 // ---------------------------------------------------------------- BF16 MFMA
 // Same arrangement with v_mfma_f32_32x32x16_bf16; pairs whose Gram-based d^2
 // falls below 1e-3 of the norm sum are recomputed from the FP32 input rows.
-__global__ void __launch_bounds__(256) k_gram_bf16(const TestDesc* __restrict__ descs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_gram_bf16(const TestDesc* __restrict__ descs,
                                                    const int64_t* __restrict__ offs, int ntests) {
   __shared__ float smem[HALF * TILE_LDS > TILE * LDS_ROW_BF16 ? HALF * TILE_LDS
                                                               : TILE * LDS_ROW_BF16];

@@ -72,8 +72,8 @@ struct SplitDraw {
 // are produced in parallel, a chunk of MCH items at a time, into LDS; wave 0
 // then runs the selection scan (one lane per split) over the chunk while waves
 // 1-3 draw the next chunk.
-constexpr int MCH = 64;
-constexpr int MSPL = 64;
+constexpr int MCH = 128;  // items per drawn chunk
+constexpr int MSPL = 32;  // split columns per workgroup (lanes 0..31 of wave 0 scan)
 
 __device__ inline uint32_t scaled_draw(uint32_t lo, uint32_t hi, uint32_t m) {
   const uint64_t p_lo = (uint64_t)lo * m, p_hi = (uint64_t)hi * m;
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ des
   // Selection scan.  Because v_t <= n - t - 1, the test v_t < need already keeps
   // every remaining item once need == n - t and none once need == 0.
   const int64_t b = col0 + lane;
-  const bool drawn = b < d.B;
+  const bool drawn = lane < MSPL && b < d.B;
   const int nx = d.nx, ntot = (int)n;
   const int64_t BP = d.B_pad;
   uint32_t need = (uint32_t)nx;

@@ -9,7 +9,7 @@
 
 namespace et {
 
-constexpr int ROWCHUNK = 128;
+constexpr int ROWCHUNK = COLSUM_ROWS;
 
 __device__ inline float load_in_f32(const TestDesc& d, int64_t t, int k) {
   return t < d.nx ? ((const float*)d.X)[t * d.p + k] : ((const float*)d.Y)[(t - d.nx) * d.p + k];

@@ -70,10 +70,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.ty = (int32_t)((r.ny + TILE - 1) / TILE);
   d.nt = d.tx + d.ty;
   d.ntiles = d.nt * (d.nt + 1) / 2;
-  // bf16 planes of the centred blocks: hi + lo keeps 16 significant bits, an error of
-  // at most 2^-17 of each centred entry (the FP32 blocks themselves carry ~2^-24 of the
-  // uncentred entry, which is of the same absolute size); one plane for the BF16 form
-  // would keep 8 bits.
+  // fp16 planes of the centred blocks: hi + lo 2^-11 keeps ~22 significant bits of each
+  // centred entry (one plane would keep 11).
   d.splits = r.prec == ETEST_PREC_F32 ? 2
              : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 2) : 1;
   d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
@@ -82,7 +80,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   for (int i = 0; i < d.nt; ++i) nrk += (d.nt - i + d.kc - 1) / d.kc;
   d.n_rowk = nrk;
   const int64_t n = r.nx + r.ny;
-  d.nrowchunks = (int32_t)((n + 127) / 128);
+  d.nrowchunks = (int32_t)((n + COLSUM_ROWS - 1) / COLSUM_ROWS);
   d.B = r.B;
   d.B_pad = (r.B + 1 + NP - 1) / NP * NP;
   // split chunks per resampling workgroup: the MFMA kernel holds two accumulator sets
@@ -133,7 +131,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
   P.wg[S_GRAM_F32] = r.prec == ETEST_PREC_F32 ? d.ntiles : 0;
   P.wg[S_GRAM_BF16] = r.prec == ETEST_PREC_BF16_REFINED ? d.ntiles : 0;
-  P.wg[S_MEMBER] = d.B_pad / 64;  // 64 split columns per workgroup
+  P.wg[S_MEMBER] = d.B_pad / 32;  // 32 split columns per workgroup
   P.wg[S_ROWSUM] = (npad + 255) / 256;
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
   P.wg[S_CENTER_SPLIT] = f64 ? 0 : d.ntiles;
