@@ -1,27 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X permutation two-sample test.
 
-One step = one whole test on device-resident synthetic inputs: staging, the
-three blocks (Gram on MFMA + epilogue), block sums and observed statistic,
-centring, the B-split stream, all B resampled statistics, threshold, count and
-p-value (every stage of the hot path).  Default workload: energy distance,
-FP32 form, X 2000 x 1000 ~ N(0, I), Y 2000 x 1000 with mean 0.05 on the first 50
-coordinates, B = 10^4 (metric: resampled statistics per second).
+One step = one whole test (or batch of tests) on device-resident synthetic inputs:
+staging, the three blocks (Gram on MFMA + epilogue), block sums and observed
+statistic, centring, the split stream, all resampled statistics, threshold, count
+and p-value -- every stage of the hot path.
 
-Prints ONE JSON line on stdout.  Per-stage device times come from HIP events
-recorded by the library on the launch stream during the timed steps.
+Workloads (--workload):
+  plain_f32       energy distance, FP32 form, X 2000 x 1000 ~ N(0, I), Y 2000 x 1000 with
+                  mean 0.05 on the first 50 coordinates, B = 10^4        (default)
+  small_f64       100 x 10 vs 100 x 10 null case, FP64 form, B = 1000
+  precision_bf16  5000 x 4096 vs 4000 x 4096 (Y variance 1.1 on 200 coordinates), ED and
+                  Gaussian MMD (sigma^2 = p), BF16-refined form, B = 10^4; the FP32 form of
+                  the same tests is timed beside it
+  batched         256 independent ED tests (nx, ny in [50, 1500], p in {20, 100, 500},
+                  B = 2000) in one graph-captured batch; tuned work shapes; the same tests
+                  run one by one are timed beside it
+  serving         Poisson stream of tests (200/s by default) through the continuous-batching
+                  server; latency p50 / p99 and served tests per second
+
+Prints ONE JSON line on stdout.  Per-stage device times come from HIP events recorded by
+the library on the launch stream.
 """
 import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "permuted statistics/sec and Gram TFLOP/s vs plain FP32; serving p50/p99 latency"
-PEAK = {"hbm_GBs": 8000.0, "bf16_TF": 2500.0, "fp32_TF": 157.3, "fp64_TF": 78.6}
+PEAK = {"hbm_GBs": 8000.0, "bf16_TF": 2500.0, "fp16_TF": 2500.0, "fp32_TF": 157.3,
+        "fp64_TF": 78.6}
 
 
 def log(*a):
@@ -38,102 +51,121 @@ def packed_pairs(nx, ny):
     return nx * (nx - 1) / 2 + ny * (ny - 1) / 2 + nx * ny
 
 
-def run_single(args, wl, kinds):
-    import numpy as np
+def to_dev(X, Y, prec):
     import torch
-
-    from paper_2406_06488_amd import api
-
-    X, Y = wl.data()
-    dt = torch.float64 if wl.prec == "f64" else torch.float32
+    dt = torch.float64 if prec == "f64" else torch.float32
     Xd = torch.from_numpy(X).to("cuda:0", dt)
     Yd = torch.from_numpy(Y).to("cuda:0", dt)
     torch.cuda.synchronize()
+    return Xd, Yd
 
-    def step():
-        out = []
-        for k in kinds:
-            out.append(api.run(Xd, Yd, wl.B, wl.perm_seed, k, wl.prec, wl.gamma()))
-        return out
 
-    for _ in range(args.warmup):
-        step()
+def timed(fn, steps, warmup, profile=True):
+    """Run fn warmup + steps times; returns (seconds for the timed steps, stage profile)."""
+    import torch
+
+    from paper_2406_06488_amd import api
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
-    api.profile_enable(True)
+    if profile:
+        api.profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
+    for _ in range(steps):
+        out = fn()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = api.profile_read()
-    api.profile_enable(False)
-    return (t1 - t0), prof, res, X, Y
+    prof = api.profile_read() if profile else None
+    if profile:
+        api.profile_enable(False)
+    return t1 - t0, prof, out
 
 
-def cpu_baseline(wl, kinds, budget_s):
-    """The FP64 oracle on the host: blocks once, then resampled splits for ~budget_s seconds;
-    the full-test rate is projected from the measured block and per-split times."""
+def per_launch(prof):
+    return {k: (v[0] / max(v[1], 1)) for k, v in prof.items()}
+
+
+def roofline(stage_ms, tests, prec):
+    """Dominant kernel's algorithmic rate against its peak.  tests: list of (nx, ny, p, B)
+    processed per launch of each stage."""
+    gflops = sum(gram_flops(nx, ny, p) for nx, ny, p, B in tests)
+    upd = sum(packed_pairs(nx, ny) * B for nx, ny, p, B in tests)
+    gram_tf = gflops / (stage_ms["blocks"] * 1e-3) / 1e12
+    res_tf = 2.0 * upd / (stage_ms["resampling"] * 1e-3) / 1e12
+    if stage_ms["resampling"] >= stage_ms["blocks"]:
+        if prec == "f64":
+            r = {"bound": "alu", "achieved": res_tf, "peak": PEAK["fp64_TF"], "unit": "TFLOP/s"}
+        else:
+            r = {"bound": "mfma", "achieved": res_tf, "peak": PEAK["fp16_TF"], "unit": "TFLOP/s"}
+        r["kernel"] = "resampling (k_perm)"
+        r["algorithmic"] = ("2 flops per (distinct off-diagonal block entry, split) = %.4g per "
+                            "launch" % (2 * upd))
+    else:
+        peak = {"f64": PEAK["fp64_TF"], "f32": PEAK["fp32_TF"], "bf16r": PEAK["bf16_TF"]}[prec]
+        r = {"bound": "alu" if prec == "f64" else "mfma", "achieved": gram_tf, "peak": peak,
+             "unit": "TFLOP/s", "kernel": "blocks (k_gram / k_dist_f64)",
+             "algorithmic": "2p flops per distinct Gram entry = %.4g per launch" % gflops}
+    r["frac"] = r["achieved"] / r["peak"]
+    r["traffic"] = None
+    return r, gram_tf, res_tf
+
+
+def base_line(args, wl_name, value, elapsed, steps, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "permuted statistics/s", "n_gpus": 1,
+            "steps": steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": dict(workload=wl_name, **config)}
+
+
+# ---------------------------------------------------------------------------- CPU oracle
+
+def cpu_baseline(tests, budget_s, label):
+    """The FP64 oracle on the host: for each sampled test, blocks once and as many resampled
+    splits as the time budget allows; the full-test rate is projected from the measured
+    block and per-split times.  tests: list of (X, Y, B, seed, kind, gamma)."""
     import numpy as np
 
     import oracle
-
-    X, Y = wl.data()
-    X = X.astype(np.float64)
-    Y = Y.astype(np.float64)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    total_blocks = 0.0
-    total_split = 0.0
-    m_done = 0
-    for k in kinds:
-        kind = oracle.ED if k == "ed" else oracle.MMD
+    tot_time = 0.0
+    tot_stats = 0
+    done = 0
+    detail = []
+    per = budget_s / max(len(tests), 1)
+    t_start = time.perf_counter()
+    for X, Y, B, seed, kind, gamma in tests:
+        if time.perf_counter() - t_start > budget_s:
+            break
+        X = X.astype(np.float64)
+        Y = Y.astype(np.float64)
+        k = oracle.ED if kind == "ed" else oracle.MMD
         t0 = time.perf_counter()
-        XX, YY, XY = oracle.blocks(X, Y, kind, wl.gamma(), threads)
+        XX, YY, XY = oracle.blocks(X, Y, k, gamma, threads)
         tb = time.perf_counter() - t0
-        m = max(threads, 8)
+        m = min(B, max(threads, 8))
         t0 = time.perf_counter()
-        oracle.perm_stats_listed(XX, YY, XY, wl.perm_seed, list(range(m)), kind, threads)
+        oracle.perm_stats_listed(XX, YY, XY, seed, list(range(m)), k, threads)
         tp = (time.perf_counter() - t0) / m
-        # spend what is left of the budget on more splits for a steadier per-split time
-        more = int(max(0.0, budget_s / len(kinds) - tb - tp * m) / max(tp, 1e-9))
-        more = min(more, wl.B)
+        more = int(min(B, max(0.0, per - tb - tp * m) / max(tp, 1e-9)))
         if more > m:
             t0 = time.perf_counter()
-            oracle.perm_stats_listed(XX, YY, XY, wl.perm_seed, list(range(more)), kind, threads)
+            oracle.perm_stats_listed(XX, YY, XY, seed, list(range(more)), k, threads)
             tp = (time.perf_counter() - t0) / more
-            m = more
-        total_blocks += tb
-        total_split += tp
-        m_done += m
-        del XX, YY, XY
-    full = total_blocks + total_split * wl.B
-    return {"value": len(kinds) * wl.B / full, "unit": "permuted statistics/s", "cores": threads,
+        tot_time += tb + tp * B
+        tot_stats += B
+        done += 1
+        detail.append("blocks %.2f s + %.3g s/split x %d measured" % (tb, tp, max(m, more)))
+    return {"value": tot_stats / tot_time, "unit": "permuted statistics/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%s: blocks once + %d of %d splits per statistic (%s), projected to the "
-                      "full test; blocks %.2f s, %.4f s per split" %
-                      (wl.name, m_done // len(kinds), wl.B, "+".join(kinds), total_blocks,
-                       total_split)}
+            "sample": "%s: %d test(s); per test the blocks once plus a bounded number of "
+                      "splits, projected to all B splits (%s)" % (label, done,
+                                                                  "; ".join(detail[:4]))}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain_f32",
-                    choices=["plain_f32", "small_f64", "precision_bf16"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py is single-process; WORLD_SIZE > 1 is not supported", file=sys.stderr)
-        sys.exit(2)
+# ---------------------------------------------------------------------------- workloads
 
-    from paper_2406_06488_amd import inputs
-
+def run_single(args):
+    from paper_2406_06488_amd import api, inputs
     if args.workload == "plain_f32":
         wl, kinds = inputs.plain_f32(), ["ed"]
     elif args.workload == "small_f64":
@@ -142,49 +174,204 @@ def main():
         wl = inputs.precision_bf16()
         kinds = wl.kinds
     log("workload", wl.name, "kinds", kinds, "steps", args.steps, "warmup", args.warmup)
-    elapsed, prof, res, X, Y = run_single(args, wl, kinds)
-    ms_step = 1e3 * elapsed / args.steps
+    X, Y = wl.data()
+    Xd, Yd = to_dev(X, Y, wl.prec)
+
+    def step(prec=wl.prec):
+        return [api.run(Xd, Yd, wl.B, wl.perm_seed, k, prec, wl.gamma()) for k in kinds]
+
+    elapsed, prof, res = timed(step, args.steps, args.warmup)
+    stage = per_launch(prof)
+    log("stage ms per test:", json.dumps({k: round(v, 4) for k, v in stage.items()}))
+    shape = [(wl.nx, wl.ny, wl.p, wl.B)]
+    roof, gram_tf, res_tf = roofline(stage, shape, wl.prec)
     value = len(kinds) * wl.B * args.steps / elapsed
-    stage_ms = {k: (v[0] / max(v[1], 1)) for k, v in prof.items()}  # per launch of the stage
-    log("stage ms per test:", json.dumps({k: round(v, 4) for k, v in stage_ms.items()}))
-
-    nx, ny, p, B = wl.nx, wl.ny, wl.p, wl.B
-    gflops = gram_flops(nx, ny, p)
-    gram_peak = {"f64": PEAK["fp64_TF"], "f32": PEAK["fp32_TF"], "bf16r": PEAK["bf16_TF"]}[wl.prec]
-    gram_tf = gflops / (stage_ms["blocks"] * 1e-3) / 1e12
-    upd = packed_pairs(nx, ny) * B
-    res_tf = 2.0 * upd / (stage_ms["resampling"] * 1e-3) / 1e12
-    if stage_ms["resampling"] >= stage_ms["blocks"]:
-        if wl.prec == "f64":
-            roof = {"bound": "alu", "achieved": res_tf, "peak": PEAK["fp64_TF"], "unit": "TFLOP/s"}
-        else:
-            roof = {"bound": "mfma", "achieved": res_tf, "peak": PEAK["bf16_TF"], "unit": "TFLOP/s"}
-        roof["kernel"] = "resampling (k_perm)"
-        roof["algorithmic"] = "2 flops per (distinct off-diagonal block entry, split): %.4g" % (2 * upd)
-    else:
-        roof = {"bound": "mfma", "achieved": gram_tf, "peak": gram_peak, "unit": "TFLOP/s",
-                "kernel": "blocks (k_gram)",
-                "algorithmic": "2p flops per distinct Gram entry: %.4g" % gflops}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-
-    line = {
-        "metric": METRIC, "value": value, "unit": "permuted statistics/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "bf16r": "bf16"}[wl.prec], "data": "synthetic",
-        "config": {"workload": wl.name, "nx": nx, "ny": ny, "p": p, "B": B,
-                   "statistics": kinds, "precision": wl.prec},
-        "gram_tflops": gram_tf,
-        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
-        "p_values": [r["p_value"] for r in res],
-        "roofline": roof,
-    }
+    line = base_line(args, wl.name, value, elapsed, args.steps,
+                     {"f64": "f64", "f32": "f32", "bf16r": "bf16"}[wl.prec],
+                     {"nx": wl.nx, "ny": wl.ny, "p": wl.p, "B": wl.B, "statistics": kinds,
+                      "precision": wl.prec})
+    line.update({"gram_tflops": gram_tf, "resampling_tflops": res_tf,
+                 "stage_ms": {k: round(v, 5) for k, v in stage.items()},
+                 "p_values": [r["p_value"] for r in res], "roofline": roof})
+    if wl.prec == "bf16r":
+        # the plain FP32 form on the same tests
+        e32, p32, _ = timed(lambda: step("f32"), max(2, args.steps // 2), 1)
+        s32 = per_launch(p32)
+        _, g32, r32 = roofline(s32, shape, "f32")
+        line["f32_form"] = {"ms_per_step": 1e3 * e32 / max(2, args.steps // 2),
+                            "gram_tflops": g32, "resampling_tflops": r32,
+                            "stage_ms": {k: round(v, 5) for k, v in s32.items()}}
+        line["speedup_vs_f32_form"] = line["f32_form"]["ms_per_step"] / line["ms_per_step"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(wl, kinds, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(
+            [(X, Y, wl.B, wl.perm_seed, k, wl.gamma()) for k in kinds], args.cpu_seconds,
+            wl.name)
     else:
         line["cpu_baseline"] = None
+    return line
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    from paper_2406_06488_amd import api, autotune, inputs
+    tests = inputs.batched_tests()
+    log("batched: %d tests, generating inputs" % len(tests))
+    data, reqs, keep = [], [], []
+    for w in tests:
+        X, Y = w.data()
+        Xd, Yd = to_dev(X, Y, w.prec)
+        data.append((X, Y))
+        keep += [Xd, Yd]
+        reqs.append(api.make_request(Xd, Yd, w.B, w.perm_seed, "ed", w.prec))
+    # tune the resampling work shape per size bucket on representative tests
+    buckets = []
+    for lo, hi in ((0, 1024), (1024, 2048), (2048, 1 << 31)):
+        idx = [i for i, w in enumerate(tests) if lo <= w.nx + w.ny < hi]
+        if not idx:
+            continue
+        i = idx[len(idx) // 2]
+        buckets.append({"prec": "f32", "n_lo": lo, "n_hi": hi, "X": keep[2 * i],
+                        "Y": keep[2 * i + 1], "B": tests[i].B, "kind": "ed"})
+    rules = autotune.tune(buckets, reps=2, log=log)
+    log("tuned:", [(r["n_lo"], r["n_hi"], r["kc"], r["cc"]) for r in rules])
+    elapsed, _, outs = timed(lambda: api.batch(reqs), args.steps, args.warmup, profile=False)
+    total_B = sum(w.B for w in tests)
+    value = total_B * args.steps / elapsed
+    # stage times of the same batch through the non-graph path (one launch per stage)
+    _, prof, _ = timed(lambda: api.batch(reqs), 2, 0, profile=True)
+    stage = per_launch(prof)
+    shape = [(w.nx, w.ny, w.p, w.B) for w in tests]
+    roof, gram_tf, res_tf = roofline(stage, shape, "f32")
+    # the same tests one by one (plain path)
+    seq_steps = max(1, args.steps // 4)
+
+    def seq():
+        return [api.run(keep[2 * i], keep[2 * i + 1], w.B, w.perm_seed, "ed", w.prec,
+                        with_perm_stats=False) for i, w in enumerate(tests)]
+    e_seq, _, seq_out = timed(seq, seq_steps, 1, profile=False)
+    same = all(a["count_ge"] == b["count_ge"] and a["statistic"] == b["statistic"]
+               for a, b in zip(outs, seq_out))
+    line = base_line(args, "ed_f32_batch256_B2000", value, elapsed, args.steps, "f32",
+                     {"tests": len(tests), "B": 2000, "nx_ny_range": [50, 1500],
+                      "p": [20, 100, 500], "precision": "f32", "graph": True})
+    line.update({"gram_tflops": gram_tf, "resampling_tflops": res_tf,
+                 "stage_ms": {k: round(v, 5) for k, v in stage.items()}, "roofline": roof,
+                 "sequential_ms_per_step": 1e3 * e_seq / seq_steps,
+                 "speedup_vs_sequential": (e_seq / seq_steps) / (elapsed / args.steps),
+                 "batch_equals_sequential": same,
+                 "tuning": [{k: r[k] for k in ("n_lo", "n_hi", "kc", "cc")} for r in rules]})
+    if not args.no_cpu_baseline:
+        sample = [(data[i][0], data[i][1], w.B, w.perm_seed, "ed", 0.0)
+                  for i, w in enumerate(tests[:16])]
+        line["cpu_baseline"] = cpu_baseline(sample, args.cpu_seconds, "batch256 (first tests)")
+    else:
+        line["cpu_baseline"] = None
+    return line
+
+
+def run_serving(args):
+    import numpy as np
+    import torch
+
+    from paper_2406_06488_amd import api, inputs
+    stream = inputs.serving_stream(rate=args.rate, duration=args.duration)
+    log("serving: %d requests over %.0f s at %.0f/s" % (len(stream), args.duration, args.rate))
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(5)
+    half = 1 << 27
+    pool = torch.randn(2 * half, generator=g, device="cuda:0", dtype=torch.float32)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(6))
+    srv = api.Server(memory_budget_bytes=int(args.budget_gb * (1 << 30)), max_resident=64,
+                     max_queue=1 << 20)
+    lat = {}
+    submitted = {}
+    done_t = {}
+    lock = threading.Lock()
+    stop = threading.Event()
+
+    def collector():
+        while not (stop.is_set() and not submitted):
+            with lock:
+                ids = list(submitted.keys())
+            for rid in ids:
+                r = srv.poll(rid)
+                if r is not None:
+                    now = time.perf_counter()
+                    with lock:
+                        t_arr = submitted.pop(rid)
+                        lat[rid] = now - t_arr
+                        done_t[rid] = (now, r)
+            time.sleep(0.0005)
+
+    th = threading.Thread(target=collector, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for t_arr, w in stream:
+        n_x, n_y = w.nx * w.p, w.ny * w.p
+        ox = int(rng.integers(0, half - n_x))
+        oy = int(rng.integers(0, half - n_y))
+        X = pool[ox:ox + n_x].view(w.nx, w.p)
+        Y = (pool[half + oy:half + oy + n_y] + w.mean_shift).view(w.ny, w.p)
+        torch.cuda.current_stream().synchronize()
+        now = time.perf_counter() - t0
+        if now < t_arr:
+            time.sleep(t_arr - now)
+        kind = w.kinds[0]
+        rid = srv.submit(X, Y, w.B, w.perm_seed, kind, "bf16r", w.gamma() if kind == "mmd" else 0.0)
+        with lock:
+            submitted[rid] = t0 + t_arr
+    t_last = time.perf_counter()
+    stop.set()
+    th.join()
+    t_end = max(v[0] for v in done_t.values())
+    srv.close()
+    L = np.array(sorted(lat.values())) * 1e3
+    served = len(lat) / (t_end - t0)
+    total_B = sum(w.B for _, w in stream)
+    line = base_line(args, "serving_poisson%d_%ds" % (args.rate, args.duration),
+                     total_B / (t_end - t0), t_end - t0, 1, "bf16",
+                     {"rate_per_s": args.rate, "duration_s": args.duration,
+                      "requests": len(stream), "nx_ny_range": [100, 20000],
+                      "p_range": [10, 2000], "B": [1000, 10000], "statistics": ["ed", "mmd"],
+                      "precision": "bf16r"})
+    line.update({"p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
+                 "mean_ms": float(L.mean()), "max_ms": float(L.max()),
+                 "tests_per_s": served, "offered_per_s": len(stream) / args.duration,
+                 "submit_lag_s": t_last - t0 - stream[-1][0], "roofline": None,
+                 "cpu_baseline": None})
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain_f32",
+                    choices=["plain_f32", "small_f64", "precision_bf16", "batched", "serving"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--duration", type=float, default=20.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-process; WORLD_SIZE > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("plain_f32", "small_f64", "precision_bf16"):
+        line = run_single(args)
+    elif args.workload == "batched":
+        line = run_batched(args)
+    else:
+        line = run_serving(args)
     print(json.dumps(line), flush=True)
 
 

@@ -217,6 +217,20 @@ etest_status etest_profile_enable(int32_t on);
 /* Accumulated milliseconds and launch counts per stage (arrays of n <= 7 entries). */
 etest_status etest_profile_read(double* ms, int64_t* launches, int32_t n);
 
+/* ---- Tuning of the resampling stage's work shape ---- */
+
+/* Rule for tests of precision `prec` with n_lo <= nx + ny < n_hi: each resampling workgroup
+   covers `kc` column tiles of 128 pooled items (1..256) and `cc` chunks of 256 splits
+   (1..2 for the FP32 / BF16 forms, 1..8 for FP64).  Rules are matched in the order they
+   were added; unmatched tests use the built-in default.  cc never changes results; kc
+   regroups the FP32 partial sums of the resampling stage, so different kc values can
+   differ at rounding level.  A test's results depend only on its own parameters and the
+   rule that matches it, never on what it is batched with.  Process-wide. */
+etest_status etest_tune_set(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t kc, int32_t cc);
+
+/* Remove every tuning rule. */
+etest_status etest_tune_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

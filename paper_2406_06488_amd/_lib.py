@@ -64,6 +64,8 @@ SIGNATURES = [
     ("etest_validate", c_i32, [ctypes.POINTER(Request)]),
     ("etest_profile_enable", c_i32, [c_i32]),
     ("etest_profile_read", c_i32, [ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), c_i32]),
+    ("etest_tune_set", c_i32, [c_i32, c_i64, c_i64, c_i32, c_i32]),
+    ("etest_tune_clear", c_i32, []),
 ]
 
 STAGES = ["staging", "blocks", "splits", "sums", "centring", "resampling", "finalize"]

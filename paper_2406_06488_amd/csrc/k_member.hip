@@ -80,7 +80,9 @@ __device__ inline uint32_t scaled_draw(uint32_t lo, uint32_t hi, uint32_t m) {
   return (uint32_t)((p_hi + (p_lo >> 32)) >> 32);  // floor(u * m / 2^64), u = hi:lo
 }
 
-__global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ descs,
+constexpr int MTHREADS = 512;  // wave 0 scans, waves 1..7 draw
+
+__global__ void __launch_bounds__(MTHREADS) k_member(const TestDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ offs, int ntests) {
   __shared__ uint32_t V[2][MCH][MSPL];
   const int ti = find_test(offs, ntests, blockIdx.x);
@@ -92,7 +94,7 @@ __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ des
   const int64_t ybase = (int64_t)d.tx * TILE;
   uint32_t* Z = d.Z;
   // words that hold no item, and the non-drawn columns (identity / padding)
-  for (int64_t e = tid; e < (int64_t)nwords * MSPL; e += 256) {
+  for (int64_t e = tid; e < (int64_t)nwords * MSPL; e += MTHREADS) {
     const int w = (int)(e / MSPL);
     const int64_t c = col0 + e % MSPL;
     const bool gap = w < xw ? (int64_t)w * 32 >= d.nx : (int64_t)(w - xw) * 32 >= d.ny;
@@ -122,7 +124,7 @@ __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ des
       if (t + 1 < n) V[buf][2 * bi + 1][s] = scaled_draw(r.z, r.w, (uint32_t)(n - t - 1));
     }
   };
-  draw_chunk(0, 0, tid, 256);
+  draw_chunk(0, 0, tid, MTHREADS);
   __syncthreads();
   // Selection scan.  Because v_t <= n - t - 1, the test v_t < need already keeps
   // every remaining item once need == n - t and none once need == 0.
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(256) k_member(const TestDesc* __restrict__ des
   uint32_t word = 0;
   for (int ch = 0; ch < nch; ++ch) {
     if (wave != 0) {
-      if (ch + 1 < nch) draw_chunk(ch + 1, (ch + 1) & 1, tid - 64, 192);
+      if (ch + 1 < nch) draw_chunk(ch + 1, (ch + 1) & 1, tid - 64, MTHREADS - 64);
     } else if (drawn) {
       const int t0 = ch * MCH;
       const int kend = min(MCH, ntot - t0);
@@ -184,7 +186,8 @@ __global__ void __launch_bounds__(256) k_member_public(int64_t nx, int64_t ny, u
 
 // blocks: split columns / MSPL workgroups per test
 void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
-  if (blocks > 0) hipLaunchKernelGGL(k_member, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_member, dim3((unsigned)blocks), dim3(MTHREADS), 0, st, d, offs, n);
 }
 void launch_member_public(int64_t nx, int64_t ny, uint64_t seed, int64_t b0, int64_t count,
                           uint32_t* words, hipStream_t st) {

@@ -31,9 +31,17 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
   const int64_t n = (int64_t)d.nx + d.ny;
   const int64_t t0 = (int64_t)rc * ROWCHUNK;
   const int64_t t1 = t0 + ROWCHUNK < n ? t0 + ROWCHUNK : n;
-  double s = 0.0;
-  for (int64_t t = t0; t < t1; ++t) s += (double)load_in_f32(d, t, k);
-  d.colpart[(int64_t)rc * d.p + k] = s;
+  // four independent running sums (rows t0 + 4i + r) keep several loads in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t t = t0;
+  for (; t + 4 <= t1; t += 4) {
+    s0 += (double)load_in_f32(d, t, k);
+    s1 += (double)load_in_f32(d, t + 1, k);
+    s2 += (double)load_in_f32(d, t + 2, k);
+    s3 += (double)load_in_f32(d, t + 3, k);
+  }
+  for (; t < t1; ++t) s0 += (double)load_in_f32(d, t, k);
+  d.colpart[(int64_t)rc * d.p + k] = (s0 + s1) + (s2 + s3);
 }
 
 __global__ void __launch_bounds__(256) k_colmean(const TestDesc* __restrict__ descs,

@@ -56,6 +56,29 @@ etest_status validate_request(const etest_request& r) {
 }
 
 
+// ------------------------------------------------------------------ tuning rules
+struct TuneRule {
+  int32_t prec;
+  int64_t n_lo, n_hi;
+  int32_t kc, cc;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneRule> g_tune;
+
+// Resampling work shape for a test: (column tiles per workgroup, chunks per workgroup).
+static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
+  *kc = 8;
+  *cc = r.prec == ETEST_PREC_F64 ? MAX_CC : 2;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int64_t n = r.nx + r.ny;
+  for (const TuneRule& t : g_tune)
+    if (t.prec == r.prec && n >= t.n_lo && n < t.n_hi) {
+      *kc = t.kc;
+      *cc = t.cc;
+      return;
+    }
+}
+
 TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   TestPlan P;
   TestDesc& d = P.d;
@@ -75,7 +98,9 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.splits = r.prec == ETEST_PREC_F32 ? 2
              : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 2) : 1;
   d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
-  d.kc = (int32_t)(kc_override > 0 ? kc_override : 8);
+  int32_t kc_t, cc_t;
+  tuned_shape(r, &kc_t, &cc_t);
+  d.kc = (int32_t)(kc_override > 0 ? kc_override : kc_t);
   int nrk = 0;
   for (int i = 0; i < d.nt; ++i) nrk += (d.nt - i + d.kc - 1) / d.kc;
   d.n_rowk = nrk;
@@ -85,7 +110,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.B_pad = (r.B + 1 + NP - 1) / NP * NP;
   // split chunks per resampling workgroup: the MFMA kernel holds two accumulator sets
   const int cc_max = r.prec == ETEST_PREC_F64 ? MAX_CC : 2;
-  d.cc = (int32_t)std::min<int64_t>(std::min(env_int("ETEST_CC", cc_max, 1, MAX_CC), cc_max),
+  d.cc = (int32_t)std::min<int64_t>(std::min(env_int("ETEST_CC", cc_t, 1, MAX_CC), cc_max),
                                     d.B_pad / NP);
   d.seed = r.seed;
   d.gamma = r.kind == ETEST_MMD ? r.gamma : 0.0;
@@ -551,6 +576,23 @@ using namespace et;
 extern "C" {
 
 const char* etest_last_error(void) { return g_err.c_str(); }
+
+etest_status etest_tune_set(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t kc, int32_t cc) {
+  if (prec != ETEST_PREC_F64 && prec != ETEST_PREC_F32 && prec != ETEST_PREC_BF16_REFINED)
+    return set_error(ETEST_EINVAL, "unknown precision");
+  const int cc_max = prec == ETEST_PREC_F64 ? MAX_CC : 2;
+  if (n_lo < 0 || n_hi <= n_lo || kc < 1 || kc > 256 || cc < 1 || cc > cc_max)
+    return set_error(ETEST_EINVAL, "bad tuning rule");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.push_back(TuneRule{prec, n_lo, n_hi, kc, cc});
+  return ETEST_OK;
+}
+
+etest_status etest_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return ETEST_OK;
+}
 
 etest_status etest_profile_enable(int32_t on) {
   g_prof.on = on != 0;
