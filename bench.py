@@ -85,7 +85,7 @@ def per_launch(prof):
     return {k: (v[0] / max(v[1], 1)) for k, v in prof.items()}
 
 
-def roofline(stage_ms, tests, prec):
+def roofline(stage_ms, tests, prec, workload=None):
     """Dominant kernel's algorithmic rate against its peak.  tests: list of (nx, ny, p, B)
     processed per launch of each stage."""
     gflops = sum(gram_flops(nx, ny, p) for nx, ny, p, B in tests)
@@ -97,17 +97,51 @@ def roofline(stage_ms, tests, prec):
             r = {"bound": "alu", "achieved": res_tf, "peak": PEAK["fp64_TF"], "unit": "TFLOP/s"}
         else:
             r = {"bound": "mfma", "achieved": res_tf, "peak": PEAK["fp16_TF"], "unit": "TFLOP/s"}
-        r["kernel"] = "resampling (k_perm)"
+        r["kernel"] = "k_perm_f64" if prec == "f64" else "k_perm_mfma"
         r["algorithmic"] = ("2 flops per (distinct off-diagonal block entry, split) = %.4g per "
                             "launch" % (2 * upd))
     else:
         peak = {"f64": PEAK["fp64_TF"], "f32": PEAK["fp32_TF"], "bf16r": PEAK["bf16_TF"]}[prec]
         r = {"bound": "alu" if prec == "f64" else "mfma", "achieved": gram_tf, "peak": peak,
-             "unit": "TFLOP/s", "kernel": "blocks (k_gram / k_dist_f64)",
+             "unit": "TFLOP/s",
+             "kernel": {"f64": "k_dist_f64", "f32": "k_gram_f32", "bf16r": "k_gram_bf16"}[prec],
              "algorithmic": "2p flops per distinct Gram entry = %.4g per launch" % gflops}
     r["frac"] = r["achieved"] / r["peak"]
-    r["traffic"] = None
+    r["traffic"] = measured_traffic(r["kernel"], workload) if workload else None
     return r, gram_tf, res_tf
+
+
+KERNEL_SOURCES = {"k_gram_f32": ["k_gram.hip", "common.h"],
+                  "k_gram_bf16": ["k_gram.hip", "common.h"],
+                  "k_dist_f64": ["k_gram.hip", "common.h"],
+                  "k_perm_mfma": ["k_perm.hip", "common.h"],
+                  "k_perm_f64": ["k_perm.hip", "common.h"]}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+
+
+def source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2406_06488_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, or None when there is none
+    for this kernel and workload or the kernel's source changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+        blob = text[text.index("```json") + 7:]
+        table = json.loads(blob[:blob.index("```")])
+    except (OSError, ValueError):
+        return None
+    e = table.get("%s|%s" % (kernel, workload))
+    if not e or e.get("source_sha256") != source_hash(kernel):
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
 
 
 def base_line(args, wl_name, value, elapsed, steps, dtype, config):
@@ -184,7 +218,7 @@ def run_single(args):
     stage = per_launch(prof)
     log("stage ms per test:", json.dumps({k: round(v, 4) for k, v in stage.items()}))
     shape = [(wl.nx, wl.ny, wl.p, wl.B)]
-    roof, gram_tf, res_tf = roofline(stage, shape, wl.prec)
+    roof, gram_tf, res_tf = roofline(stage, shape, wl.prec, wl.name)
     value = len(kinds) * wl.B * args.steps / elapsed
     line = base_line(args, wl.name, value, elapsed, args.steps,
                      {"f64": "f64", "f32": "f32", "bf16r": "bf16"}[wl.prec],
@@ -244,7 +278,7 @@ def run_batched(args):
     _, prof, _ = timed(lambda: api.batch(reqs), 2, 0, profile=True)
     stage = per_launch(prof)
     shape = [(w.nx, w.ny, w.p, w.B) for w in tests]
-    roof, gram_tf, res_tf = roofline(stage, shape, "f32")
+    roof, gram_tf, res_tf = roofline(stage, shape, "f32", "ed_f32_batch256_B2000")
     # the same tests one by one (plain path)
     seq_steps = max(1, args.steps // 4)
 
@@ -346,6 +380,22 @@ def run_serving(args):
     return line
 
 
+def copy_calibration():
+    """A plain device-to-device copy of known size, run under the same HBM counters as the
+    kernels: FETCH_SIZE / WRITE_SIZE per copy dispatch divided by 256 MiB gives each
+    counter's scale."""
+    import torch
+    n = 64 << 20  # float32 elements: 256 MiB each way
+    src = torch.randn(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +408,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=20.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -366,6 +418,9 @@ def main():
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py is single-process; WORLD_SIZE > 1 is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.workload in ("plain_f32", "small_f64", "precision_bf16"):
         line = run_single(args)
     elif args.workload == "batched":

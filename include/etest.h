@@ -136,8 +136,11 @@ etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* 
 etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void* stream);
 
 /* n independent tests in one batched pass: every stage is one launch covering all tests,
-   and the launch sequence is captured once into a HIP graph and replayed.  outs: host
-   array of n results.  Each test's result equals what etest_run gives for it alone. */
+   and the launch sequence is captured once into a HIP graph and replayed while the same
+   request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,
+   each holding its workspace until evicted.  With stage timing on (etest_profile_enable)
+   the batch runs without a graph so that the stages can be timed.  outs: host array of n
+   results.  Each test's result equals what etest_run gives for it alone. */
 etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, etest_result* outs);
 
 /* ---- Stage-level calls (each step of the path, for parity checks) ---- */
@@ -207,7 +210,7 @@ etest_status etest_footprint(const etest_request* req, int64_t* bytes);
 /* Check a request's arguments without touching the device (same rules as every call). */
 etest_status etest_validate(const etest_request* req);
 
-/* Stage timing of the calling thread's etest_run / ed_test / mmd_test calls: when on, HIP
+/* Stage timing of the calling thread's etest_run / etest_batch / ed_test / mmd_test calls: when on, HIP
    events on the call's stream bracket each stage and their elapsed times accumulate.
    Stages: 0 staging (column means, cast, norms), 1 blocks (Gram + epilogue), 2 split stream,
    3 block sums + observed statistic, 4 centring, 5 resampling, 6 statistics + p-value.

@@ -28,6 +28,7 @@ constexpr int TILE_WORDS = TILE / 32;
 constexpr int NP = 256;              // split columns per resampling chunk
 constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
 constexpr int COLSUM_ROWS = 128;     // pooled rows per partial column sum
+constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
 enum { KIND_ED = 0, KIND_MMD = 1 };

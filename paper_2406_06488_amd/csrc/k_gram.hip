@@ -233,17 +233,42 @@ k_gram_bf16(const TestDesc* __restrict__ descs,
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
+  // 1024 chunks of 8 bf16 per operand and 64-wide slice: thread tid owns rows
+  // (tid >> 3) + 32 s, chunk (tid & 7); the next slice is loaded into registers while the
+  // current one is multiplied.
+  const int lrow = tid >> 3, c8 = (tid & 7) * 8;
+  const uint16_t* ga = Wa + (int64_t)lrow * d.p_pad + c8;
+  const uint16_t* gb = Wb + (int64_t)lrow * d.p_pad + c8;
+  const int64_t rstep = (int64_t)32 * d.p_pad;
+  uint4 pa0 = *(const uint4*)(ga), pa1 = *(const uint4*)(ga + rstep);
+  uint4 pa2 = *(const uint4*)(ga + 2 * rstep), pa3 = *(const uint4*)(ga + 3 * rstep);
+  uint4 pb0 = *(const uint4*)(gb), pb1 = *(const uint4*)(gb + rstep);
+  uint4 pb2 = *(const uint4*)(gb + 2 * rstep), pb3 = *(const uint4*)(gb + 3 * rstep);
   for (int k0 = 0; k0 < d.p_pad; k0 += 64) {
     __syncthreads();
-    for (int s = 0; s < 4; ++s) {
-      const int q = tid + 256 * s;  // 1024 chunks of 8 bf16 per operand
-      const int row = q >> 3, c8 = (q & 7) * 8;
-      const uint4 va = *(const uint4*)(Wa + (int64_t)row * d.p_pad + k0 + c8);
-      const uint4 vb = *(const uint4*)(Wb + (int64_t)row * d.p_pad + k0 + c8);
-      *(uint4*)(As + row * LDS_ROW_BF16 + c8) = va;
-      *(uint4*)(Bs + row * LDS_ROW_BF16 + c8) = vb;
-    }
+    uint16_t* la = As + lrow * LDS_ROW_BF16 + c8;
+    uint16_t* lb = Bs + lrow * LDS_ROW_BF16 + c8;
+    *(uint4*)(la) = pa0;
+    *(uint4*)(la + 32 * LDS_ROW_BF16) = pa1;
+    *(uint4*)(la + 64 * LDS_ROW_BF16) = pa2;
+    *(uint4*)(la + 96 * LDS_ROW_BF16) = pa3;
+    *(uint4*)(lb) = pb0;
+    *(uint4*)(lb + 32 * LDS_ROW_BF16) = pb1;
+    *(uint4*)(lb + 64 * LDS_ROW_BF16) = pb2;
+    *(uint4*)(lb + 96 * LDS_ROW_BF16) = pb3;
     __syncthreads();
+    if (k0 + 64 < d.p_pad) {
+      const uint16_t* na = ga + k0 + 64;
+      const uint16_t* nb2 = gb + k0 + 64;
+      pa0 = *(const uint4*)(na);
+      pa1 = *(const uint4*)(na + rstep);
+      pa2 = *(const uint4*)(na + 2 * rstep);
+      pa3 = *(const uint4*)(na + 3 * rstep);
+      pb0 = *(const uint4*)(nb2);
+      pb1 = *(const uint4*)(nb2 + rstep);
+      pb2 = *(const uint4*)(nb2 + 2 * rstep);
+      pb3 = *(const uint4*)(nb2 + 3 * rstep);
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       bf16x8 av[2], bv[2];

@@ -16,9 +16,11 @@ namespace et {
 __device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // one 32 x 32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -67,100 +69,109 @@ struct SplitDraw {
 // Internal layout Z[w][col]: columns 0..B-1 drawn splits, B the identity split,
 // the rest zero; words cover padded pooled positions (X tiles, then Y tiles).
 //
-// One workgroup serves MSPL consecutive split columns.  The scaled draws
-// v_t = floor(u_t (n - t) / 2^64) do not depend on the running count, so they
-// are produced in parallel, a chunk of MCH items at a time, into LDS; wave 0
-// then runs the selection scan (one lane per split) over the chunk while waves
-// 1-3 draw the next chunk.
-constexpr int MCH = 128;  // items per drawn chunk
-constexpr int MSPL = 32;  // split columns per workgroup (lanes 0..31 of wave 0 scan)
+// One workgroup serves MEMBER_SPLITS consecutive split columns and walks the pooled
+// tiles in order (one tile = 128 padded positions = 4 words).  The scaled draws
+// v_t = floor(u_t (n - t) / 2^64) do not depend on the running count, so waves 1..4
+// produce the next tile's draws into LDS while wave 0 runs the selection scan (one
+// lane per split) over the current one.  Positions without an item (tile padding)
+// hold v = 0xFFFFFFFF, which is never below need (< 2^31), so the scan is the same
+// branch-free step for every position and writes whole words.
+constexpr int MTHREADS = 320;  // wave 0 scans, waves 1..4 draw
+constexpr int MSPL = MEMBER_SPLITS;
 
 __device__ inline uint32_t scaled_draw(uint32_t lo, uint32_t hi, uint32_t m) {
   const uint64_t p_lo = (uint64_t)lo * m, p_hi = (uint64_t)hi * m;
   return (uint32_t)((p_hi + (p_lo >> 32)) >> 32);  // floor(u * m / 2^64), u = hi:lo
 }
 
-constexpr int MTHREADS = 512;  // wave 0 scans, waves 1..7 draw
-
 __global__ void __launch_bounds__(MTHREADS) k_member(const TestDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ offs, int ntests) {
-  __shared__ uint32_t V[2][MCH][MSPL];
+  __shared__ uint32_t V[2][TILE][MSPL];
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
   const int64_t col0 = (blockIdx.x - offs[ti]) * MSPL;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n = (int64_t)d.nx + d.ny;
   const int xw = d.tx * TILE_WORDS, nwords = d.nt * TILE_WORDS;
-  const int64_t ybase = (int64_t)d.tx * TILE;
   uint32_t* Z = d.Z;
-  // words that hold no item, and the non-drawn columns (identity / padding)
-  for (int64_t e = tid; e < (int64_t)nwords * MSPL; e += MTHREADS) {
-    const int w = (int)(e / MSPL);
-    const int64_t c = col0 + e % MSPL;
-    const bool gap = w < xw ? (int64_t)w * 32 >= d.nx : (int64_t)(w - xw) * 32 >= d.ny;
-    if (c >= d.B) {
+  const int64_t BP = d.B_pad;
+  // non-drawn columns: the identity split (column B) and zero padding
+  if (col0 + MSPL > d.B) {
+    for (int e = tid; e < nwords * MSPL; e += MTHREADS) {
+      const int w = e / MSPL;
+      const int64_t c = col0 + e % MSPL;
+      if (c < d.B) continue;
       uint32_t v = 0;
       if (c == d.B && w < xw) {
         const int64_t cnt = d.nx - (int64_t)w * 32;
         v = cnt >= 32 ? 0xFFFFFFFFu : (cnt > 0 ? ((1u << cnt) - 1u) : 0u);
       }
-      Z[(int64_t)w * d.B_pad + c] = v;
-    } else if (gap) {
-      Z[(int64_t)w * d.B_pad + c] = 0u;
+      Z[(int64_t)w * BP + c] = v;
     }
   }
   if (col0 >= d.B) return;
   const uint32_t k0 = (uint32_t)d.seed, k1 = (uint32_t)(d.seed >> 32);
-  const int nch = (int)((n + MCH - 1) / MCH);
-  auto draw_chunk = [&](int ch, int buf, int first, int stride) {
-    for (int q = first; q < (MCH / 2) * MSPL; q += stride) {
-      const int s = q % MSPL, bi = q / MSPL;
-      const int64_t t = (int64_t)ch * MCH + 2 * bi;
-      const uint64_t bb = (uint64_t)(col0 + s);
-      if (t >= n || (int64_t)bb >= d.B) continue;
-      const uint4 r = philox4x32_10(make_uint4((uint32_t)(t >> 1), (uint32_t)bb,
-                                               (uint32_t)(bb >> 32), 0u), k0, k1);
-      V[buf][2 * bi][s] = scaled_draw(r.x, r.y, (uint32_t)(n - t));
-      if (t + 1 < n) V[buf][2 * bi + 1][s] = scaled_draw(r.z, r.w, (uint32_t)(n - t - 1));
+  // pooled tile ch holds items t_lo .. t_lo + cnt - 1 at padded positions 0 .. cnt - 1
+  auto tile_items = [&](int ch, int64_t* t_lo, int* cnt) {
+    if (ch < d.tx) {
+      *t_lo = (int64_t)ch * TILE;
+      *cnt = (int)min<int64_t>(TILE, d.nx - *t_lo);
+    } else {
+      *t_lo = d.nx + (int64_t)(ch - d.tx) * TILE;
+      *cnt = (int)min<int64_t>(TILE, n - *t_lo);
     }
   };
-  draw_chunk(0, 0, tid, MTHREADS);
+  auto draw_tile = [&](int ch, int buf, int first, int stride) {
+    int64_t t_lo;
+    int cnt;
+    tile_items(ch, &t_lo, &cnt);
+    // Philox counters t/2 covering the tile's items; a pair may straddle two tiles
+    const int64_t c_lo = t_lo >> 1, c_hi = (t_lo + cnt - 1) >> 1;
+    const int np = (int)(c_hi - c_lo + 1);
+#pragma unroll 2
+    for (int q = first; q < np * MSPL; q += stride) {
+      const int s = q % MSPL;
+      const int64_t ci = c_lo + q / MSPL;
+      const uint64_t bb = (uint64_t)(col0 + s);
+      if ((int64_t)bb >= d.B) continue;
+      const uint4 r = philox4x32_10(make_uint4((uint32_t)ci, (uint32_t)bb,
+                                               (uint32_t)(bb >> 32), 0u), k0, k1);
+      const int64_t t0 = 2 * ci;
+      if (t0 >= t_lo) V[buf][t0 - t_lo][s] = scaled_draw(r.x, r.y, (uint32_t)(n - t0));
+      if (t0 + 1 < t_lo + cnt)
+        V[buf][t0 + 1 - t_lo][s] = scaled_draw(r.z, r.w, (uint32_t)(n - t0 - 1));
+    }
+    for (int q = first; q < (TILE - cnt) * MSPL; q += stride)
+      V[buf][cnt + q / MSPL][q % MSPL] = 0xFFFFFFFFu;
+  };
+  draw_tile(0, 0, tid, MTHREADS);
   __syncthreads();
   // Selection scan.  Because v_t <= n - t - 1, the test v_t < need already keeps
   // every remaining item once need == n - t and none once need == 0.
   const int64_t b = col0 + lane;
   const bool drawn = lane < MSPL && b < d.B;
-  const int nx = d.nx, ntot = (int)n;
-  const int64_t BP = d.B_pad;
-  uint32_t need = (uint32_t)nx;
-  uint32_t word = 0;
-  for (int ch = 0; ch < nch; ++ch) {
+  uint32_t need = (uint32_t)d.nx;
+  for (int ch = 0; ch < d.nt; ++ch) {
     if (wave != 0) {
-      if (ch + 1 < nch) draw_chunk(ch + 1, (ch + 1) & 1, tid - 64, MTHREADS - 64);
+      if (ch + 1 < d.nt) draw_tile(ch + 1, (ch + 1) & 1, tid - 64, MTHREADS - 64);
     } else if (drawn) {
-      const int t0 = ch * MCH;
-      const int kend = min(MCH, ntot - t0);
+      const uint32_t(*Vb)[MSPL] = V[ch & 1];
 #pragma unroll
-      for (int k8 = 0; k8 < MCH; k8 += 8) {
-        uint32_t v[8];
+      for (int w = 0; w < TILE_WORDS; ++w) {
+        uint32_t word = 0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = V[ch & 1][k8 + e][lane];
+        for (int k8 = 0; k8 < 32; k8 += 8) {
+          uint32_t v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int k = k8 + e;
-          if (k < kend) {
-            const int t = t0 + k;
+          for (int e = 0; e < 8; ++e) v[e] = Vb[32 * w + k8 + e][lane];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
             const uint32_t take = v[e] < need ? 1u : 0u;
             need -= take;
-            const int pos = t < nx ? t : (int)ybase + (t - nx);
-            word |= take << (pos & 31);
-            // flush at the end of a word or of the X / Y part
-            if ((pos & 31) == 31 || t == nx - 1 || t == ntot - 1) {
-              Z[(int64_t)(pos >> 5) * BP + b] = word;
-              word = 0;
-            }
+            word |= take << (k8 + e);
           }
         }
+        Z[(int64_t)(ch * TILE_WORDS + w) * BP + b] = word;
       }
     }
     __syncthreads();
@@ -184,7 +195,7 @@ __global__ void __launch_bounds__(256) k_member_public(int64_t nx, int64_t ny, u
   }
 }
 
-// blocks: split columns / MSPL workgroups per test
+// blocks: B_pad / MEMBER_SPLITS workgroups per test
 void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
   if (blocks > 0)
     hipLaunchKernelGGL(k_member, dim3((unsigned)blocks), dim3(MTHREADS), 0, st, d, offs, n);

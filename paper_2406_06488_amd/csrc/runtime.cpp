@@ -64,6 +64,12 @@ struct TuneRule {
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneRule> g_tune;
+static uint64_t g_tune_gen = 0;  // bumped on every change (guarded by g_tune_mu)
+
+static uint64_t tune_generation() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune_gen;
+}
 
 // Resampling work shape for a test: (column tiles per workgroup, chunks per workgroup).
 static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
@@ -156,7 +162,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
   P.wg[S_GRAM_F32] = r.prec == ETEST_PREC_F32 ? d.ntiles : 0;
   P.wg[S_GRAM_BF16] = r.prec == ETEST_PREC_BF16_REFINED ? d.ntiles : 0;
-  P.wg[S_MEMBER] = d.B_pad / 32;  // 32 split columns per workgroup
+  P.wg[S_MEMBER] = d.B_pad / MEMBER_SPLITS;
   P.wg[S_ROWSUM] = (npad + 255) / 256;
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
   P.wg[S_CENTER_SPLIT] = f64 ? 0 : d.ntiles;
@@ -495,6 +501,7 @@ static etest_status run_host(int kind, int prec, const void* X, int64_t nx, cons
 // while the same list (same shapes, seeds and device pointers) is submitted again.
 struct GraphEntry {
   std::vector<etest_request> key;
+  uint64_t tune_gen = 0;  // tuning rules the captured work shapes came from
   Batch batch;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -518,8 +525,9 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
                                     etest_result* outs) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   GraphEntry* hit = nullptr;
+  const uint64_t gen = tune_generation();
   for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
-    if (same_requests(it->key, reqs, n)) {
+    if (it->tune_gen == gen && same_requests(it->key, reqs, n)) {
       g_graphs.splice(g_graphs.begin(), g_graphs, it);
       hit = &g_graphs.front();
       break;
@@ -527,6 +535,7 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
   if (!hit) {
     GraphEntry g;
     g.key.assign(reqs, reqs + n);
+    g.tune_gen = gen;
     etest_status s = build_batch(reqs, n, false, &g.batch);
     if (s != ETEST_OK) return s;
     // Workspace and descriptors are placed before capture; the graph holds kernels only.
@@ -585,12 +594,14 @@ etest_status etest_tune_set(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t kc
     return set_error(ETEST_EINVAL, "bad tuning rule");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.push_back(TuneRule{prec, n_lo, n_hi, kc, cc});
+  ++g_tune_gen;
   return ETEST_OK;
 }
 
 etest_status etest_tune_clear(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.clear();
+  ++g_tune_gen;
   return ETEST_OK;
 }
 
@@ -694,6 +705,8 @@ etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, ete
     etest_status s = validate_request(reqs[t]);
     if (s != ETEST_OK) return s;
   }
+  // With stage timing on, the batch runs eagerly so that the stage events are recorded.
+  if (g_prof.on) return run_device(reqs, n, (hipStream_t)stream, outs);
   return run_batch_graph(reqs, n, (hipStream_t)stream, outs);
 }
 
