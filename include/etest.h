@@ -58,7 +58,7 @@ extern "C" {
 
 typedef enum {
   ETEST_OK = 0,
-  ETEST_EINVAL = 1,      /* nx < 1, ny < 1, p < 1, B < 0, NULL pointer, gamma <= 0 or
+  ETEST_EINVAL = 1,      /* nx < 1, ny < 1, p < 1, B < 0 or B >= 2^31 - 1, NULL pointer, gamma <= 0 or
                             non-finite, nx + ny > 2^31 - 1, bad request field        */
   ETEST_ENONFINITE = 2,  /* X or Y holds a NaN or an Inf                                 */
   ETEST_ENOMEM = 3,      /* device memory, or the server's memory budget, exhausted      */

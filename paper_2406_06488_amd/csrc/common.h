@@ -27,8 +27,10 @@ constexpr int TILE = 128;            // edge of a stored block tile
 constexpr int TILE_WORDS = TILE / 32;
 constexpr int NP = 256;              // split columns per resampling chunk
 constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
-constexpr int COLSUM_ROWS = 128;     // pooled rows per partial column sum
+constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
 constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
+constexpr int FLAG_COUNT = 4;        // int32 index of the 64-bit (count, finished WGs) word
+constexpr int FLAG_WORDS = 8;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
 enum { KIND_ED = 0, KIND_MMD = 1 };
@@ -65,6 +67,7 @@ struct TestDesc {
   double* part;
   double* pstat;
   int32_t* flags;    // [0] non-finite input seen, [1] refined pair count
+  // flags[FLAG_COUNT..+1]: exceedance count (low half) and finished workgroups (high half)
   double* perm_out;
   DevResult* result;
 };

@@ -39,6 +39,8 @@ __device__ inline uint32_t pack_h2(_Float16 a, _Float16 b) {
 __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict__ descs,
                                                       const int64_t* __restrict__ offs,
                                                       int ntests) {
+  // centring constants of the tile's 128 rows and 128 columns (0 for padding)
+  __shared__ double crow[TILE], ccol[TILE];
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
   const int t = (int)(blockIdx.x - offs[ti]);
@@ -49,16 +51,44 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
   const double inv_n = 1.0 / n;
   const double c0 = d.obs[4] / (n * n);
   const double scale = d.obs[5];
+  const double half = i == j ? 0.5 : 1.0;
   const int S = d.splits;
+  {
+    const int r = threadIdx.x & (TILE - 1);
+    const int blk = threadIdx.x < TILE ? i : j;
+    const int64_t pa = (int64_t)blk * TILE + r;
+    const double c = (d.rsum[pa * 2] + d.rsum[pa * 2 + 1]) * inv_n;
+    if (threadIdx.x < TILE) crow[r] = c;
+    else ccol[r] = c;
+  }
+  __syncthreads();
   const float* Dt = (const float*)d.D + (int64_t)t * TILE * TILE;
   uint16_t* P = (uint16_t*)d.planes + (int64_t)t * S * TILE * TILE;
-  for (int q = threadIdx.x; q < TILE * TILE / 8; q += 256) {
+  // every load of the thread first (16 x 16 B in flight), then the conversions
+  constexpr int NQ = TILE * TILE / 8 / 256;
+  float4 raw[NQ][2];
+#pragma unroll
+  for (int it = 0; it < NQ; ++it) {
+    const int q = threadIdx.x + 256 * it;
     const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
     const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
+    raw[it][0] = *(const float4*)(Dt + r * TILE + c0l);
+    raw[it][1] = *(const float4*)(Dt + r * TILE + c0l + 4);
+  }
+#pragma unroll
+  for (int it = 0; it < NQ; ++it) {
+    const int q = threadIdx.x + 256 * it;
+    const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
+    const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
+    const float v[8] = {raw[it][0].x, raw[it][0].y, raw[it][0].z, raw[it][0].w,
+                        raw[it][1].x, raw[it][1].y, raw[it][1].z, raw[it][1].w};
+    const double ca = crow[r];
     _Float16 hi[8], lo[8];
+#pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const double x = center_value(d, i, j, r, c0l + e, rows_i, rows_j,
-                                    (double)Dt[r * TILE + c0l + e], inv_n, c0) * scale;
+      const int col = c0l + e;
+      double x = 0.0;
+      if (r < rows_i && col < rows_j) x = ((((double)v[e] - ca) - ccol[col]) + c0) * half * scale;
       hi[e] = (_Float16)x;
       lo[e] = (_Float16)((x - (double)hi[e]) * 2048.0);
     }

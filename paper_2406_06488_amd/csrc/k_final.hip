@@ -9,56 +9,76 @@
 
 namespace et {
 
-__global__ void __launch_bounds__(256) k_pstat(const TestDesc* __restrict__ descs,
-                                               const int64_t* __restrict__ offs, int ntests) {
-  const int ti = find_test(offs, ntests, blockIdx.x);
-  const TestDesc d = descs[ti];
-  const int64_t col = (blockIdx.x - offs[ti]) * 256 + threadIdx.x;
-  if (col >= d.B_pad) return;
-  double q = 0.0;
-  for (int rk = 0; rk < d.n_rowk; ++rk) q += d.part[(int64_t)rk * d.B_pad + col];
+// One workgroup per 64 split columns: 16 groups of waves each sum every 16th row range,
+// then wave 0 adds the 16 group sums in order.  Every workgroup also evaluates the
+// identity column B with the same loads in the same order, so all of them hold the
+// threshold bit for bit as the column's own workgroup computes it.  Exceedances are
+// counted with one integer atomic per workgroup; the last workgroup of a test writes the
+// result.
+constexpr int PS_GROUPS = 16;
+
+__device__ inline double split_statistic(const TestDesc& d, double q) {
   if (d.prec != PREC_F64) q /= d.obs[5];  // undo the power-of-two scale of the fp16 planes
   const double a = 1.0 / d.nx + 1.0 / d.ny;
   const double coef = a * a * 2.0;
-  d.pstat[col] = d.kind == KIND_ED ? -coef * q : coef * q;
+  return d.kind == KIND_ED ? -coef * q : coef * q;
 }
 
-// One workgroup per test.
-__global__ void __launch_bounds__(256) k_final(const TestDesc* __restrict__ descs,
-                                               const int64_t* __restrict__ sel, int ntests) {
-  __shared__ int64_t cnt[256];
-  if (sel && sel[blockIdx.x + 1] == sel[blockIdx.x]) return;
-  const TestDesc d = descs[blockIdx.x];
-  const int tid = threadIdx.x;
-  const double thr = d.pstat[d.B];
-  const bool bad = d.flags[0] != 0 || d.flags[2] != 0;
-  int64_t c = 0;
-  for (int64_t b = tid; b < d.B; b += 256) {
-    const double v = d.pstat[b];
-    c += v >= thr ? 1 : 0;
-    if (d.perm_out && !bad) d.perm_out[b] = v;
+__global__ void __launch_bounds__(64 * PS_GROUPS) k_pstat(const TestDesc* __restrict__ descs,
+                                                          const int64_t* __restrict__ offs,
+                                                          int ntests) {
+  __shared__ double red[PS_GROUPS][65];  // [.][64]: the identity column
+  const int ti = find_test(offs, ntests, blockIdx.x);
+  const TestDesc d = descs[ti];
+  const int64_t wg = blockIdx.x - offs[ti];
+  const int64_t nwg = offs[ti + 1] - offs[ti];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t col = wg * 64 + c;
+  double s = 0.0;
+  for (int rk = g; rk < d.n_rowk; rk += PS_GROUPS) s += d.part[(int64_t)rk * d.B_pad + col];
+  red[g][c] = s;
+  if (c == 0) {
+    double sb = 0.0;
+    for (int rk = g; rk < d.n_rowk; rk += PS_GROUPS) sb += d.part[(int64_t)rk * d.B_pad + d.B];
+    red[g][64] = sb;
   }
-  cnt[tid] = c;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) cnt[tid] += cnt[tid + s];
-    __syncthreads();
+  if (g != 0) return;
+  double q = 0.0, qb = 0.0;
+  for (int k = 0; k < PS_GROUPS; ++k) {
+    q += red[k][c];
+    qb += red[k][64];
   }
-  if (tid == 0) {
-    DevResult r;
-    r.statistic = d.obs[3];
-    r.threshold = thr;
-    r.count_ge = cnt[0];
-    r.B = d.B;
-    r.p_value = (1.0 + (double)cnt[0]) / (1.0 + (double)d.B);
-    r.n_refined = d.flags[1];
-    r.status = d.flags[0] ? 2 : (d.flags[2] ? 1 : 0);
-    r.pad = 0;
-    if (bad) {
-      r.statistic = __builtin_nan("");
-      r.p_value = __builtin_nan("");
+  const double v = split_statistic(d, q), thr = split_statistic(d, qb);
+  d.pstat[col] = v;
+  const bool bad = d.flags[0] != 0 || d.flags[2] != 0;
+  const bool drawn = col < d.B;
+  if (drawn && d.perm_out && !bad) d.perm_out[col] = v;
+  const uint64_t ge = __ballot(drawn && v >= thr);
+  // one 64-bit atomic carries both the count (low 32 bits; B < 2^31) and the number of
+  // finished workgroups (high 32 bits), so the last workgroup's returned value already
+  // holds every other workgroup's count: no fence is needed
+  unsigned long long* cnt = (unsigned long long*)(d.flags + FLAG_COUNT);
+  if (c == 0) {
+    const unsigned long long add = (1ull << 32) | (unsigned long long)__popcll(ge);
+    const unsigned long long old = atomicAdd(cnt, add);
+    if ((int64_t)(old >> 32) == nwg - 1) {
+      const int64_t count = (int64_t)((old + add) & 0xFFFFFFFFull);
+      DevResult r;
+      r.statistic = d.obs[3];
+      r.threshold = thr;
+      r.count_ge = count;
+      r.B = d.B;
+      r.p_value = (1.0 + (double)count) / (1.0 + (double)d.B);
+      r.n_refined = d.flags[1];
+      r.status = d.flags[0] ? 2 : (d.flags[2] ? 1 : 0);
+      r.pad = 0;
+      if (bad) {
+        r.statistic = __builtin_nan("");
+        r.p_value = __builtin_nan("");
+      }
+      *d.result = r;
     }
-    *d.result = r;
   }
 }
 
@@ -122,10 +142,8 @@ __global__ void __launch_bounds__(256) k_member_import(const TestDesc* __restric
 }
 
 void launch_pstat(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
-  if (blocks > 0) hipLaunchKernelGGL(k_pstat, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
-}
-void launch_final(hipStream_t st, const TestDesc* d, const int64_t* sel, int n) {
-  hipLaunchKernelGGL(k_final, dim3((unsigned)n), dim3(256), 0, st, d, sel, n);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_pstat, dim3((unsigned)blocks), dim3(64 * PS_GROUPS), 0, st, d, offs, n);
 }
 void launch_unpack(bool f64, int64_t elems, hipStream_t st, const TestDesc* d, void* xx, void* yy,
                    void* xy) {

@@ -18,7 +18,8 @@ __device__ inline double load_in_f64(const TestDesc& d, int64_t t, int k) {
   return t < d.nx ? ((const double*)d.X)[t * d.p + k] : ((const double*)d.Y)[(t - d.nx) * d.p + k];
 }
 
-// Partial column sums over chunks of ROWCHUNK pooled rows (FP64).
+// Partial column sums over chunks of ROWCHUNK pooled rows (FP64).  All ROWCHUNK loads of a
+// thread are issued before the (fixed-order) sum, so they are in flight together.
 __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
@@ -30,29 +31,36 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
   if (k >= d.p) return;
   const int64_t n = (int64_t)d.nx + d.ny;
   const int64_t t0 = (int64_t)rc * ROWCHUNK;
-  const int64_t t1 = t0 + ROWCHUNK < n ? t0 + ROWCHUNK : n;
-  // four independent running sums (rows t0 + 4i + r) keep several loads in flight
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int64_t t = t0;
-  for (; t + 4 <= t1; t += 4) {
-    s0 += (double)load_in_f32(d, t, k);
-    s1 += (double)load_in_f32(d, t + 1, k);
-    s2 += (double)load_in_f32(d, t + 2, k);
-    s3 += (double)load_in_f32(d, t + 3, k);
-  }
-  for (; t < t1; ++t) s0 += (double)load_in_f32(d, t, k);
-  d.colpart[(int64_t)rc * d.p + k] = (s0 + s1) + (s2 + s3);
+  float v[ROWCHUNK];
+#pragma unroll
+  for (int r = 0; r < ROWCHUNK; ++r) v[r] = t0 + r < n ? load_in_f32(d, t0 + r, k) : 0.0f;
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < ROWCHUNK; ++r) s += (double)v[r];
+  d.colpart[(int64_t)rc * d.p + k] = s;
 }
 
-__global__ void __launch_bounds__(256) k_colmean(const TestDesc* __restrict__ descs,
-                                                 const int64_t* __restrict__ offs, int ntests) {
+// Column means: 64 columns per workgroup, 16 groups of waves each summing every 16th
+// partial, then the 16 group sums in order (a fixed order: the result is reproducible).
+constexpr int CM_GROUPS = 16;
+__global__ void __launch_bounds__(64 * CM_GROUPS) k_colmean(const TestDesc* __restrict__ descs,
+                                                            const int64_t* __restrict__ offs,
+                                                            int ntests) {
+  __shared__ double red[CM_GROUPS][64];
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
-  const int k = (int)(blockIdx.x - offs[ti]) * 256 + threadIdx.x;
-  if (k >= d.p) return;
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int k = (int)(blockIdx.x - offs[ti]) * 64 + c;
   double s = 0.0;
-  for (int rc = 0; rc < d.nrowchunks; ++rc) s += d.colpart[(int64_t)rc * d.p + k];
-  d.colmean[k] = s / (double)((int64_t)d.nx + d.ny);
+  if (k < d.p)
+    for (int rc = g; rc < d.nrowchunks; rc += CM_GROUPS) s += d.colpart[(int64_t)rc * d.p + k];
+  red[g][c] = s;
+  __syncthreads();
+  if (g == 0 && k < d.p) {
+    double t = 0.0;
+    for (int q = 0; q < CM_GROUPS; ++q) t += red[q][c];
+    d.colmean[k] = t / (double)((int64_t)d.nx + d.ny);
+  }
 }
 
 __device__ inline double wave_sum(double v) {
@@ -93,21 +101,55 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
     if (lane == 0) ((double*)d.nrm)[pos] = nrm;
   } else {
     const bool bf = d.prec == PREC_BF16R;
-    for (int k = lane; k < d.p_pad; k += 64) {
-      float v = 0.0f;
-      if (t >= 0 && k < d.p) {
-        const float x = load_in_f32(d, t, k);
-        bad |= !isfinite(x);
-        v = (float)((double)x - d.colmean[k]);
+    const float* src = t < 0 ? nullptr
+                             : (t < d.nx ? (const float*)d.X + t * d.p
+                                         : (const float*)d.Y + (t - d.nx) * d.p);
+    // four columns per lane when every row starts on a 16-byte boundary
+    const bool vec = (d.p & 3) == 0 && (((uintptr_t)d.X | (uintptr_t)d.Y) & 15) == 0;
+    if (vec) {
+      for (int k = 4 * lane; k < d.p_pad; k += 256) {
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (src && k < d.p) {
+          const float4 x = *(const float4*)(src + k);
+          bad |= !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(x.w));
+          v.x = (float)((double)x.x - d.colmean[k]);
+          v.y = (float)((double)x.y - d.colmean[k + 1]);
+          v.z = (float)((double)x.z - d.colmean[k + 2]);
+          v.w = (float)((double)x.w - d.colmean[k + 3]);
+        }
+        if (bf) {
+          const uint16_t h0 = f32_to_bf16_rn(v.x), h1 = f32_to_bf16_rn(v.y);
+          const uint16_t h2 = f32_to_bf16_rn(v.z), h3 = f32_to_bf16_rn(v.w);
+          uint2 o;
+          o.x = (uint32_t)h0 | ((uint32_t)h1 << 16);
+          o.y = (uint32_t)h2 | ((uint32_t)h3 << 16);
+          *(uint2*)((uint16_t*)d.W + pos * d.p_pad + k) = o;
+          const double r0 = bf16_to_f32(h0), r1 = bf16_to_f32(h1);
+          const double r2 = bf16_to_f32(h2), r3 = bf16_to_f32(h3);
+          nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
+        } else {
+          *(float4*)((float*)d.W + pos * d.p_pad + k) = v;
+          nrm += (((double)v.x * v.x + (double)v.y * v.y) + (double)v.z * v.z) +
+                 (double)v.w * v.w;
+        }
       }
-      if (bf) {
-        const uint16_t h = f32_to_bf16_rn(v);
-        ((uint16_t*)d.W)[pos * d.p_pad + k] = h;
-        const float r = bf16_to_f32(h);
-        nrm += (double)r * (double)r;
-      } else {
-        ((float*)d.W)[pos * d.p_pad + k] = v;
-        nrm += (double)v * (double)v;
+    } else {
+      for (int k = lane; k < d.p_pad; k += 64) {
+        float v = 0.0f;
+        if (src && k < d.p) {
+          const float x = src[k];
+          bad |= !isfinite(x);
+          v = (float)((double)x - d.colmean[k]);
+        }
+        if (bf) {
+          const uint16_t h = f32_to_bf16_rn(v);
+          ((uint16_t*)d.W)[pos * d.p_pad + k] = h;
+          const float r = bf16_to_f32(h);
+          nrm += (double)r * (double)r;
+        } else {
+          ((float*)d.W)[pos * d.p_pad + k] = v;
+          nrm += (double)v * (double)v;
+        }
       }
     }
     nrm = wave_sum(nrm);
@@ -123,9 +165,7 @@ __global__ void k_clear_flags(const TestDesc* __restrict__ descs, const int64_t*
                               int ntests) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < ntests && (offs == nullptr || offs[t + 1] > offs[t])) {
-    descs[t].flags[0] = 0;
-    descs[t].flags[1] = 0;
-    descs[t].flags[2] = 0;
+    for (int k = 0; k < FLAG_WORDS; ++k) descs[t].flags[k] = 0;
   }
 }
 
@@ -136,7 +176,8 @@ void launch_colpart(int64_t blocks, hipStream_t st, const TestDesc* d, const int
   if (blocks > 0) hipLaunchKernelGGL(k_colpart, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
 }
 void launch_colmean(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
-  if (blocks > 0) hipLaunchKernelGGL(k_colmean, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_colmean, dim3((unsigned)blocks), dim3(64 * CM_GROUPS), 0, st, d, offs, n);
 }
 void launch_stage(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
   if (blocks > 0) hipLaunchKernelGGL(k_stage, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);

@@ -10,28 +10,31 @@
 
 namespace et {
 
-__global__ void __launch_bounds__(256) k_rowsum(const TestDesc* __restrict__ descs,
-                                                const int64_t* __restrict__ offs, int ntests) {
+// Thread q < npad: same-sample part of position q; q >= npad: cross-sample part of
+// position q - npad.  One wave per workgroup so that the short grid spreads over the CUs.
+__global__ void __launch_bounds__(64) k_rowsum(const TestDesc* __restrict__ descs,
+                                               const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
-  const int64_t pos = (blockIdx.x - offs[ti]) * 256 + threadIdx.x;
   const int64_t npad = (int64_t)d.nt * TILE;
-  if (pos >= npad) return;
+  const int64_t q = (blockIdx.x - offs[ti]) * 64 + threadIdx.x;
+  if (q >= 2 * npad) return;
+  const bool cross = q >= npad;
+  const int64_t pos = cross ? q - npad : q;
   const int i = (int)(pos / TILE), r = (int)(pos % TILE);
   const double* ts = d.tsum;
   const bool isx = i < d.tx;
-  const int b0 = isx ? 0 : d.tx, b1 = isx ? d.tx : d.nt;  // own block's tile range
-  double same = 0.0, cross = 0.0;
-  for (int j = b0; j < i; ++j) same += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
-  for (int j = i; j < b1; ++j) same += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
-  if (isx) {
-    for (int j = d.tx; j < d.nt; ++j) cross += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
+  double s = 0.0;
+  if (!cross) {
+    const int b0 = isx ? 0 : d.tx, b1 = isx ? d.tx : d.nt;  // own block's tile range
+    for (int j = b0; j < i; ++j) s += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
+    for (int j = i; j < b1; ++j) s += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
+  } else if (isx) {
+    for (int j = d.tx; j < d.nt; ++j) s += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
   } else {
-    for (int j = 0; j < d.tx; ++j)
-      cross += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
+    for (int j = 0; j < d.tx; ++j) s += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
   }
-  d.rsum[pos * 2 + 0] = same;
-  d.rsum[pos * 2 + 1] = cross;
+  d.rsum[pos * 2 + (cross ? 1 : 0)] = s;
 }
 
 struct Neu {
@@ -65,17 +68,19 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
   red[0][tid][0] = sxx.s; red[0][tid][1] = sxx.c;
   red[1][tid][0] = syy.s; red[1][tid][1] = syy.c;
   red[2][tid][0] = sxy.s; red[2][tid][1] = sxy.c;
-  __syncthreads();
-  if (tid < 3) {
-    Neu a{0, 0};
-    double comp = 0.0;
-    for (int q = 0; q < 256; ++q) {
-      a.add(red[tid][q][0]);
-      comp += red[tid][q][1];
-    }
-    a.add(comp);
-    d.obs[tid] = a.value();
+  // pairwise combination of the compensated partials (fixed tree: reproducible)
+  for (int st = 128; st > 0; st >>= 1) {
+    __syncthreads();
+    if (tid < st)
+      for (int a = 0; a < 3; ++a) {
+        Neu u{red[a][tid][0], red[a][tid][1] + red[a][tid + st][1]};
+        u.add(red[a][tid + st][0]);
+        red[a][tid][0] = u.s;
+        red[a][tid][1] = u.c;
+      }
   }
+  __syncthreads();
+  if (tid < 3) d.obs[tid] = red[tid][0][0] + red[tid][0][1];
   __syncthreads();
   if (tid == 0) {
     const double nx = d.nx, ny = d.ny;
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
 }
 
 void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
-  if (blocks > 0) hipLaunchKernelGGL(k_rowsum, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+  if (blocks > 0) hipLaunchKernelGGL(k_rowsum, dim3((unsigned)blocks), dim3(64), 0, st, d, offs, n);
 }
 void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n) {
   hipLaunchKernelGGL(k_observed, dim3((unsigned)n), dim3(256), 0, st, d, sel, n);

@@ -48,7 +48,7 @@ etest_status validate_request(const etest_request& r) {
   if (r.B < 0) return set_error(ETEST_EINVAL, "B must be >= 0");
   if (r.nx + r.ny > 2147483647LL) return set_error(ETEST_EINVAL, "nx + ny must be < 2^31");
   if (r.p > 2147483647LL / 2) return set_error(ETEST_EINVAL, "p too large");
-  if (r.B > (int64_t)1 << 40) return set_error(ETEST_EINVAL, "B too large");
+  if (r.B > 2147483646LL) return set_error(ETEST_EINVAL, "B must be < 2^31 - 1");
   if (r.kind == ETEST_MMD && !(std::isfinite(r.gamma) && r.gamma > 0.0))
     return set_error(ETEST_EINVAL, "gamma must be finite and > 0");
   if (!r.X || !r.Y) return set_error(ETEST_EINVAL, "X and Y must not be NULL");
@@ -100,9 +100,10 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   d.nt = d.tx + d.ty;
   d.ntiles = d.nt * (d.nt + 1) / 2;
   // fp16 planes of the centred blocks: hi + lo 2^-11 keeps ~22 significant bits of each
-  // centred entry (one plane would keep 11).
+  // centred entry, which the FP32 form needs; one plane keeps 11, ample for the BF16 form
+  // (its operands carry 8).
   d.splits = r.prec == ETEST_PREC_F32 ? 2
-             : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 2) : 1;
+             : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 1, 1, 2) : 1;
   d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
   int32_t kc_t, cc_t;
   tuned_shape(r, &kc_t, &cc_t);
@@ -143,7 +144,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   sz[B_Z] = (size_t)(npad / 32) * d.B_pad * 4;
   sz[B_PART] = (size_t)d.n_rowk * d.B_pad * 8;
   sz[B_PSTAT] = (size_t)d.B_pad * 8;
-  sz[B_FLAGS] = 16;
+  sz[B_FLAGS] = FLAG_WORDS * 4;
   sz[B_RESULT] = sizeof(DevResult);
   sz[B_PERMOUT] = 0;  // set by build_batch when an internal output is needed
   size_t o = 0;
@@ -157,13 +158,13 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
 
   const bool f32like = !f64;
   P.wg[S_COLPART] = f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0;
-  P.wg[S_COLMEAN] = f32like ? (r.p + 255) / 256 : 0;
+  P.wg[S_COLMEAN] = f32like ? (r.p + 63) / 64 : 0;
   P.wg[S_STAGE] = npad / 4;
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
   P.wg[S_GRAM_F32] = r.prec == ETEST_PREC_F32 ? d.ntiles : 0;
   P.wg[S_GRAM_BF16] = r.prec == ETEST_PREC_BF16_REFINED ? d.ntiles : 0;
   P.wg[S_MEMBER] = d.B_pad / MEMBER_SPLITS;
-  P.wg[S_ROWSUM] = (npad + 255) / 256;
+  P.wg[S_ROWSUM] = (2 * npad + 63) / 64;  // two threads per pooled position
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
   P.wg[S_CENTER_SPLIT] = f64 ? 0 : d.ntiles;
   const int64_t perm_wg = perm_units(d, (int)(d.B_pad / NP));
@@ -171,7 +172,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   P.wg[S_PERM_S1] = (!f64 && d.splits == 1) ? perm_wg : 0;
   P.wg[S_PERM_S2] = (!f64 && d.splits == 2) ? perm_wg : 0;
   P.wg[S_PERM_S3] = (!f64 && d.splits == 3) ? perm_wg : 0;
-  P.wg[S_PSTAT] = d.B_pad / 256;
+  P.wg[S_PSTAT] = d.B_pad / 64;
   return P;
 }
 
@@ -278,7 +279,13 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   };
   const TestDesc* D = b.d_descs;
   launch_clear_flags(st, D, nullptr, n);
-  // split stream: independent of the data, so it may run beside the block stage
+  begin(0, st);
+  launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), n);
+  launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), n);
+  launch_stage(total(S_STAGE), st, D, offs(S_STAGE), n);
+  end(0, st);
+  // split stream: independent of the data, so it runs beside the block stage, whose grid
+  // leaves room on the CUs (it is forked after staging, a short memory-bound stage)
   hipStream_t ms = st;
   if (fork) {
     (void)hipEventRecord(fork->start, st);
@@ -290,11 +297,6 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   else launch_member(total(S_MEMBER), ms, D, offs(S_MEMBER), n);
   end(2, ms);
   if (fork) (void)hipEventRecord(fork->done, ms);
-  begin(0, st);
-  launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), n);
-  launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), n);
-  launch_stage(total(S_STAGE), st, D, offs(S_STAGE), n);
-  end(0, st);
   begin(1, st);
   launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n);
   launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n);
@@ -317,7 +319,6 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   end(5, st);
   begin(6, st);
   launch_pstat(total(S_PSTAT), st, D, offs(S_PSTAT), n);
-  launch_final(st, D, nullptr, n);
   end(6, st);
 }
 

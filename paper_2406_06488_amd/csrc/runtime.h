@@ -28,7 +28,6 @@ void launch_member_import(int64_t bpad, hipStream_t st, const TestDesc* d, const
 void launch_perm(int variant, int64_t blocks, hipStream_t st, const TestDesc* d,
                  const int64_t* offs, int ntests, const int32_t* pcr);
 void launch_pstat(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
-void launch_final(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
 void launch_unpack(bool f64, int64_t elems, hipStream_t st, const TestDesc* d, void* xx, void* yy,
                    void* xy);
 

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -63,6 +65,10 @@ struct etest_server {
   std::unordered_map<uint64_t, Req*> reqs;
   uint64_t next_id = 1;
   int64_t bytes_held = 0, completed = 0;
+  // scheduler time per phase (seconds) and step count, printed at destroy when the
+  // environment variable ETEST_SERVER_STATS is set
+  double t_admit = 0, t_prep = 0, t_sync = 0, t_finish = 0;
+  int64_t steps = 0;
   // device tables over the slot index space
   TestDesc* d_descs = nullptr;
   int64_t* d_offs = nullptr;   // [S_COUNT + 2][R + 1]: launch slots, then front / finish selectors
@@ -192,6 +198,12 @@ extern "C" etest_status etest_server_destroy(etest_server* S) {
   S->cv_work.notify_all();
   if (S->th.joinable()) S->th.join();
   for (auto& kv : S->reqs) delete kv.second;
+  if (getenv("ETEST_SERVER_STATS"))
+    fprintf(stderr,
+            "etest server: %lld steps, %lld completed; scheduler seconds: admit %.3f, "
+            "prepare+enqueue %.3f, device wait %.3f, finish %.3f\n",
+            (long long)S->steps, (long long)S->completed, S->t_admit, S->t_prep, S->t_sync,
+            S->t_finish);
   if (S->st) (void)hipStreamSynchronize(S->st);
   if (S->d_descs) (void)hipFree(S->d_descs);
   if (S->d_offs) (void)hipFree(S->d_offs);
@@ -224,9 +236,14 @@ void run_scheduler(etest_server* S) {
   (void)hipSetDevice(S->device);
   const int R = S->cfg.max_resident;
   std::vector<int> fresh, finishing;
+  using clk = std::chrono::steady_clock;
+  auto secs = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double>(b - a).count();
+  };
   while (true) {
     fresh.clear();
     finishing.clear();
+    clk::time_point ta;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       auto any_resident = [&] {
@@ -246,6 +263,7 @@ void run_scheduler(etest_server* S) {
         S->cv_done.notify_all();
       }
       // 1. admission in arrival order
+      ta = clk::now();
       while (!S->pending.empty()) {
         Req* q = S->pending.front();
         int slot = -1;
@@ -276,6 +294,7 @@ void run_scheduler(etest_server* S) {
         fresh.push_back(slot);
       }
     }
+    const clk::time_point tb = clk::now();
     // 2-4. one step of device work over the slot table
     int64_t* O = S->h_offs;
     memset(O, 0, sizeof(int64_t) * NSEL * (R + 1));
@@ -349,13 +368,14 @@ void run_scheduler(etest_server* S) {
       launch_perm(3, total(S_PERM_S3), st, D, offs(S_PERM_S3), R, S->d_pcr);
       if (total(SEL_FINISH) > 0) {
         launch_pstat(total(S_PSTAT), st, D, offs(S_PSTAT), R);
-        launch_final(st, D, offs(SEL_FINISH), R);
         e = hipMemcpyAsync(S->h_results, S->d_results, sizeof(DevResult) * R,
                            hipMemcpyDeviceToHost, st);
       }
       if (e == hipSuccess) e = hipGetLastError();
     }
+    const clk::time_point tc = clk::now();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const clk::time_point td = clk::now();
     {
       std::lock_guard<std::mutex> lk(S->mu);
       for (int k : fresh)
@@ -385,6 +405,11 @@ void run_scheduler(etest_server* S) {
           S->slots[(size_t)k] = nullptr;
         }
       }
+      S->t_admit += secs(ta, tb);
+      S->t_prep += secs(tb, tc);
+      S->t_sync += secs(tc, td);
+      S->t_finish += secs(td, clk::now());
+      S->steps++;
     }
     S->cv_done.notify_all();
   }

@@ -43,6 +43,7 @@ def test_struct_layouts_match_header():
     dict(nx=5, ny=0, p=3, B=10),
     dict(nx=5, ny=5, p=0, B=10),
     dict(nx=5, ny=5, p=3, B=-1),
+    dict(nx=5, ny=5, p=3, B=2**31),
     dict(nx=5, ny=5, p=3, B=10, X=None),
     dict(nx=5, ny=5, p=3, B=10, Y=None),
     dict(nx=5, ny=5, p=3, B=10, kind="mmd", gamma=0.0),
