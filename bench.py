@@ -60,8 +60,15 @@ def to_dev(X, Y, prec):
     return Xd, Yd
 
 
+LIVE_STAGES = ["blocks", "resampling"]
+
+
 def timed(fn, steps, warmup, profile=True):
-    """Run fn warmup + steps times; returns (seconds for the timed steps, stage profile)."""
+    """Run fn warmup + steps times.  Returns (seconds for the timed steps, live profile,
+    breakdown profile, last output).  During the timed steps the library brackets only the
+    two candidate dominant stages (Gram, resampling) with HIP events on their launch stream
+    ("live" times, every step); the full per-stage breakdown comes from a separate pass of
+    min(steps, 5) calls, so its extra events stay out of the timed region."""
     import torch
 
     from paper_2406_06488_amd import api
@@ -69,20 +76,27 @@ def timed(fn, steps, warmup, profile=True):
         fn()
     torch.cuda.synchronize()
     if profile:
-        api.profile_enable(True)
+        api.profile_enable(True, LIVE_STAGES)
     t0 = time.perf_counter()
     for _ in range(steps):
         out = fn()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = api.profile_read() if profile else None
+    live = breakdown = None
     if profile:
+        live = api.profile_read()
+        api.profile_enable(True)
+        for _ in range(min(steps, 5)):
+            fn()
+        torch.cuda.synchronize()
+        breakdown = api.profile_read()
         api.profile_enable(False)
-    return t1 - t0, prof, out
+    return t1 - t0, live, breakdown, out
 
 
 def per_launch(prof):
-    return {k: (v[0] / max(v[1], 1)) for k, v in prof.items()}
+    """{stage: ms per launch} for the stages that were timed."""
+    return {k: v[0] / v[1] for k, v in prof.items() if v[1] > 0}
 
 
 def roofline(stage_ms, tests, prec, workload=None):
@@ -90,6 +104,8 @@ def roofline(stage_ms, tests, prec, workload=None):
     processed per launch of each stage."""
     gflops = sum(gram_flops(nx, ny, p) for nx, ny, p, B in tests)
     upd = sum(packed_pairs(nx, ny) * B for nx, ny, p, B in tests)
+    if not stage_ms.get("blocks") or not stage_ms.get("resampling"):
+        return None, None, None
     gram_tf = gflops / (stage_ms["blocks"] * 1e-3) / 1e12
     res_tf = 2.0 * upd / (stage_ms["resampling"] * 1e-3) / 1e12
     if stage_ms["resampling"] >= stage_ms["blocks"]:
@@ -214,8 +230,10 @@ def run_single(args):
     def step(prec=wl.prec):
         return [api.run(Xd, Yd, wl.B, wl.perm_seed, k, prec, wl.gamma()) for k in kinds]
 
-    elapsed, prof, res = timed(step, args.steps, args.warmup)
+    elapsed, live, prof, res = timed(step, args.steps, args.warmup)
     stage = per_launch(prof)
+    live_ms = {k: v for k, v in per_launch(live).items() if k in LIVE_STAGES}
+    stage.update(live_ms)
     log("stage ms per test:", json.dumps({k: round(v, 4) for k, v in stage.items()}))
     shape = [(wl.nx, wl.ny, wl.p, wl.B)]
     roof, gram_tf, res_tf = roofline(stage, shape, wl.prec, wl.name)
@@ -226,11 +244,13 @@ def run_single(args):
                       "precision": wl.prec})
     line.update({"gram_tflops": gram_tf, "resampling_tflops": res_tf,
                  "stage_ms": {k: round(v, 5) for k, v in stage.items()},
+                 "stage_ms_live": sorted(live_ms),
                  "p_values": [r["p_value"] for r in res], "roofline": roof})
     if wl.prec == "bf16r":
         # the plain FP32 form on the same tests
-        e32, p32, _ = timed(lambda: step("f32"), max(2, args.steps // 2), 1)
+        e32, l32, p32, _ = timed(lambda: step("f32"), max(2, args.steps // 2), 1)
         s32 = per_launch(p32)
+        s32.update({k: v for k, v in per_launch(l32).items() if k in LIVE_STAGES})
         _, g32, r32 = roofline(s32, shape, "f32")
         line["f32_form"] = {"ms_per_step": 1e3 * e32 / max(2, args.steps // 2),
                             "gram_tflops": g32, "resampling_tflops": r32,
@@ -271,12 +291,14 @@ def run_batched(args):
                         "Y": keep[2 * i + 1], "B": tests[i].B, "kind": "ed"})
     rules = autotune.tune(buckets, reps=2, log=log)
     log("tuned:", [(r["n_lo"], r["n_hi"], r["kc"], r["cc"]) for r in rules])
-    elapsed, _, outs = timed(lambda: api.batch(reqs), args.steps, args.warmup, profile=False)
+    elapsed, _, _, outs = timed(lambda: api.batch(reqs), args.steps, args.warmup, profile=False)
     total_B = sum(w.B for w in tests)
     value = total_B * args.steps / elapsed
     # stage times of the same batch through the non-graph path (one launch per stage)
-    _, prof, _ = timed(lambda: api.batch(reqs), 2, 0, profile=True)
+    _, live, prof, _ = timed(lambda: api.batch(reqs), 2, 0, profile=True)
     stage = per_launch(prof)
+    live_ms = {k: v for k, v in per_launch(live).items() if k in LIVE_STAGES}
+    stage.update(live_ms)
     shape = [(w.nx, w.ny, w.p, w.B) for w in tests]
     roof, gram_tf, res_tf = roofline(stage, shape, "f32", "ed_f32_batch256_B2000")
     # the same tests one by one (plain path)
@@ -285,7 +307,7 @@ def run_batched(args):
     def seq():
         return [api.run(keep[2 * i], keep[2 * i + 1], w.B, w.perm_seed, "ed", w.prec,
                         with_perm_stats=False) for i, w in enumerate(tests)]
-    e_seq, _, seq_out = timed(seq, seq_steps, 1, profile=False)
+    e_seq, _, _, seq_out = timed(seq, seq_steps, 1, profile=False)
     same = all(a["count_ge"] == b["count_ge"] and a["statistic"] == b["statistic"]
                for a, b in zip(outs, seq_out))
     line = base_line(args, "ed_f32_batch256_B2000", value, elapsed, args.steps, "f32",

@@ -126,7 +126,11 @@ etest_status mmd_test_f64(const double* X, int64_t nx, const double* Y, int64_t 
 /* ---- Device buffers ---- */
 
 /* Run one test described by device pointers on `stream` (a hipStream_t, NULL = default
-   stream) and wait for it; fills the host struct `out`. */
+   stream) and wait for it; fills the host struct `out`.  The first call with a given shape
+   (kind, precision, nx, ny, p, B) on a thread launches the stages one by one; a later call
+   with a shape among that thread's last 8 replays a captured graph of the same launches
+   (see etest_batch), with this call's pointers, seed and gamma.  Results are identical
+   either way. */
 etest_status etest_run(const etest_request* req, void* stream, etest_result* out);
 
 /* Enqueue one test on `stream` and return without waiting.  d_out is a device pointer to
@@ -139,8 +143,9 @@ etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void*
    and the launch sequence is captured once into a HIP graph and replayed while the same
    request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,
    each holding its workspace until evicted.  With stage timing on (etest_profile_enable)
-   the batch runs without a graph so that the stages can be timed.  outs: host array of n
-   results.  Each test's result equals what etest_run gives for it alone. */
+   the stage events are captured into the graph (one graph per shape list and stage mask).
+   outs: host array of n results.  Each test's result equals what etest_run gives for it
+   alone. */
 etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, etest_result* outs);
 
 /* ---- Stage-level calls (each step of the path, for parity checks) ---- */
@@ -214,7 +219,9 @@ etest_status etest_validate(const etest_request* req);
    events on the call's stream bracket each stage and their elapsed times accumulate.
    Stages: 0 staging (column means, cast, norms), 1 blocks (Gram + epilogue), 2 split stream,
    3 block sums + observed statistic, 4 centring, 5 resampling, 6 statistics + p-value.
-   etest_profile_enable(1) also resets the totals. */
+   on = 0: off; 1: every stage; otherwise bits 1..7 of `on` select stages 0..6 (bit k+1 =
+   stage k), so that only the kernels of interest are bracketed by events (each event adds
+   a marker between launches).  Enabling also resets the totals. */
 etest_status etest_profile_enable(int32_t on);
 
 /* Accumulated milliseconds and launch counts per stage (arrays of n <= 7 entries). */

@@ -277,8 +277,15 @@ class Server:
         self.close()
 
 
-def profile_enable(on=True):
-    check(_lib.load().etest_profile_enable(1 if on else 0))
+def profile_enable(on=True, stages=None):
+    """Stage timing on / off; `stages`: names from _lib.STAGES to time (default: all)."""
+    if not on:
+        mode = 0
+    elif stages is None:
+        mode = 1
+    else:
+        mode = sum(1 << (_lib.STAGES.index(s) + 1) for s in stages)
+    check(_lib.load().etest_profile_enable(mode))
 
 
 def profile_read():

@@ -72,6 +72,7 @@ struct Batch {
   int64_t* d_offs = nullptr;
   DevResult* d_results = nullptr;
   double* d_perm = nullptr;      // internal perm-stat buffers (host-output calls)
+  std::vector<size_t> base;      // each test's region offset inside ws
 };
 
 // Point a plan's descriptor at its buffers inside a device region.
@@ -87,6 +88,7 @@ etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered);
 constexpr int NSTAGE = 7;
 struct StageEvents {
   hipEvent_t begin[NSTAGE], end[NSTAGE];
+  uint32_t mask = 0;  // stages (bit k = stage k) whose events are recorded
 };
 
 // Optional second stream for the split stream, which does not depend on the data:

@@ -24,6 +24,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -34,6 +35,65 @@
 using namespace et;
 
 namespace {
+
+// Best-fit arena over one device allocation made when the server starts.  Requests are
+// placed and released on the host; a region is released only after the step that
+// finished its request has synchronised, so it can be handed out again at once.
+class Arena {
+ public:
+  bool init(size_t bytes) {
+    bytes &= ~size_t(255);
+    if (bytes == 0 || hipMalloc(&base_, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      base_ = nullptr;
+      return false;
+    }
+    size_ = bytes;
+    free_[0] = bytes;
+    return true;
+  }
+  void destroy() {
+    if (base_) (void)hipFree(base_);
+    base_ = nullptr;
+    free_.clear();
+  }
+  void* alloc(size_t n) {
+    n = (n + 255) & ~size_t(255);
+    auto best = free_.end();
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n && (best == free_.end() || it->second < best->second)) best = it;
+    if (best == free_.end()) return nullptr;
+    const size_t off = best->first, rem = best->second - n;
+    free_.erase(best);
+    if (rem) free_[off + n] = rem;
+    return base_ + off;
+  }
+  bool owns(const void* p) const {
+    return base_ && (const char*)p >= base_ && (const char*)p < base_ + size_;
+  }
+  void release(void* p, size_t n) {
+    n = (n + 255) & ~size_t(255);
+    size_t off = (size_t)((char*)p - base_);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + n == next->first) {
+      n += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+};
 
 struct Req {
   uint64_t id = 0;
@@ -69,6 +129,7 @@ struct etest_server {
   // environment variable ETEST_SERVER_STATS is set
   double t_admit = 0, t_prep = 0, t_sync = 0, t_finish = 0;
   int64_t steps = 0;
+  Arena arena;  // request workspaces; the stream-ordered pool serves what does not fit
   // device tables over the slot index space
   TestDesc* d_descs = nullptr;
   int64_t* d_offs = nullptr;   // [S_COUNT + 2][R + 1]: launch slots, then front / finish selectors
@@ -117,6 +178,9 @@ extern "C" etest_status etest_server_create(const etest_server_config* cfg, etes
     return ETEST_EDEVICE;
   }
   memset(S->h_descs, 0, sizeof(TestDesc) * R);
+  // one allocation for the budget (smaller if the device cannot hold it all)
+  for (size_t b = (size_t)cfg->memory_budget_bytes; b >= ((size_t)1 << 26); b /= 2)
+    if (S->arena.init(b)) break;
   S->th = std::thread(run_scheduler, S);
   *out = S;
   return ETEST_OK;
@@ -214,6 +278,7 @@ extern "C" etest_status etest_server_destroy(etest_server* S) {
   if (S->h_pcr) (void)hipHostFree(S->h_pcr);
   if (S->h_results) (void)hipHostFree(S->h_results);
   if (S->st) (void)hipStreamDestroy(S->st);
+  S->arena.destroy();
   delete S;
   return ETEST_OK;
 }
@@ -223,6 +288,12 @@ namespace {
 // Block-entry x split updates of one split-column chunk of a request.
 double chunk_cost(const Req* q) {
   return (double)q->plan.d.ntiles * TILE * TILE * NP;
+}
+
+void release_ws(etest_server* S, Req* q) {
+  if (S->arena.owns(q->ws)) S->arena.release(q->ws, (size_t)q->footprint);
+  else (void)hipFreeAsync(q->ws, S->st);
+  q->ws = nullptr;
 }
 
 void fail_request(etest_server* S, Req* q, etest_status s, const std::string& m) {
@@ -274,8 +345,9 @@ void run_scheduler(etest_server* S) {
           }
         if (slot < 0 || S->bytes_held + q->footprint > S->cfg.memory_budget_bytes) break;
         S->pending.pop_front();
-        void* ws = nullptr;
-        hipError_t e = hipMallocAsync(&ws, (size_t)q->footprint, S->st);
+        void* ws = S->arena.alloc((size_t)q->footprint);
+        hipError_t e = hipSuccess;
+        if (!ws) e = hipMallocAsync(&ws, (size_t)q->footprint, S->st);
         if (e != hipSuccess || !ws) {
           (void)hipGetLastError();
           if (S->bytes_held == 0) {
@@ -386,7 +458,7 @@ void run_scheduler(etest_server* S) {
           Req* q = S->slots[(size_t)k];
           if (!q) continue;
           fail_request(S, q, ETEST_EDEVICE, std::string("device: ") + hipGetErrorString(e));
-          (void)hipFreeAsync(q->ws, st);
+          release_ws(S, q);
           S->bytes_held -= q->footprint;
           S->slots[(size_t)k] = nullptr;
         }
@@ -400,7 +472,7 @@ void run_scheduler(etest_server* S) {
           else q->err = etest_last_error();
           q->done = true;
           S->completed++;
-          (void)hipFreeAsync(q->ws, st);
+          release_ws(S, q);
           S->bytes_held -= q->footprint;
           S->slots[(size_t)k] = nullptr;
         }

@@ -12,8 +12,9 @@ whose oracle statistic lies within that tolerance of the oracle threshold
 
 The BF16 form rounds every coordinate to 8 significant bits, which moves a
 distance by about 0.6 * 2^-9 / sqrt(p) of itself on Gaussian data; its 1e-3
-target therefore applies to high-dimensional data (p >= 64 here), and below
-that the form is checked against the oracle run on the bf16-rounded data.
+target therefore applies to high-dimensional data (p >= 64 here).  Below that
+the form is checked on data it represents exactly (bf16_exact_pair), where
+only its own arithmetic separates it from the oracle.
 """
 import sys
 
@@ -59,16 +60,19 @@ def compare_run(g, o, prec, label="", tol=None):
     return np.flatnonzero(near)
 
 
-def bf16_round(a):
-    """float32 array -> float32 values rounded to bfloat16 (round to nearest, ties to even)."""
-    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
-
-
-def bf16_operands(X, Y):
-    """The operands the BF16 form multiplies: pooled-column-mean centred, then bf16-rounded."""
-    mean = (X.astype(np.float64).sum(0) + Y.astype(np.float64).sum(0)) / (len(X) + len(Y))
-    Xc = bf16_round((X.astype(np.float64) - mean).astype(np.float32))
-    Yc = bf16_round((Y.astype(np.float64) - mean).astype(np.float32))
-    return Xc.astype(np.float64), Yc.astype(np.float64)
+def bf16_exact_pair(X, Y):
+    """Data on which the BF16 form rounds nothing: every coordinate a multiple of 2^-4 in
+    (-16, 16) (at most 8 significant bits), and the pooled sample symmetric about 0 (each
+    drawn row is followed by its negation, plus a zero row for an odd count), so the pooled
+    column mean is exactly 0 and centring changes nothing.  Rows come from the case's
+    Gaussian draws, so shapes and ragged tails are those of the case."""
+    nx, ny = len(X), len(Y)
+    n = nx + ny
+    W = np.concatenate([X, Y]).astype(np.float64)
+    half = np.clip(np.round(W[: n // 2] * 16.0) / 16.0, -15.9375, 15.9375)
+    rows = np.empty((n, W.shape[1]))
+    rows[0:2 * (n // 2):2] = half
+    rows[1:2 * (n // 2):2] = -half
+    if n % 2:
+        rows[-1] = 0.0
+    return rows[:nx].astype(np.float32), rows[nx:].astype(np.float32)

@@ -6,7 +6,7 @@ import oracle
 from oracle import brute
 from paper_2406_06488_amd import api, inputs
 from paper_2406_06488_amd._lib import EtestError
-from tests.gpu_helpers import BF16_MIN_P, TOL, bf16_operands, compare_run, say
+from tests.gpu_helpers import BF16_MIN_P, TOL, bf16_exact_pair, compare_run, say
 
 pytestmark = pytest.mark.gpu
 
@@ -83,21 +83,14 @@ def test_full_test_matches_oracle(case, kind, prec):
     nx, ny, p, B, ds, ps_, shift = CASES[case]
     say("full", case, kind, prec, nx, ny, p, B)
     X, Y = _data(nx, ny, p, ds, prec, shift)
+    if prec == "bf16r" and p < BF16_MIN_P:
+        # below its design dimension the BF16 form is pinned on data it represents exactly
+        X, Y = bf16_exact_pair(X, Y)
     gamma = 1.0 / p
     g = api.run(_dev(X, prec), _dev(Y, prec), B, ps_, kind, prec, gamma)
     torch.cuda.synchronize()
-    if prec == "bf16r" and p < BF16_MIN_P:
-        # below its design dimension the BF16 form is pinned on the data it multiplies
-        if g["n_refined"]:
-            pytest.skip("%d near pairs recomputed from the unrounded rows" % g["n_refined"])
-        Xo, Yo = bf16_operands(X, Y)
-        o = oracle.run_test(Xo, Yo, B, ps_, KIND[kind], gamma)
-        # what remains is the form's own arithmetic (FP32 Gram epilogue, one fp16 plane of
-        # the centred blocks), held to the form's tolerance
-        near = compare_run(g, o, prec, "case %d %s bf16-rounded" % (case, kind))
-    else:
-        o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, ps_, KIND[kind], gamma)
-        near = compare_run(g, o, prec, "case %d %s %s" % (case, kind, prec))
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, ps_, KIND[kind], gamma)
+    near = compare_run(g, o, prec, "case %d %s %s" % (case, kind, prec))
     if len(near):
         say("near-ties within tolerance:", near.tolist())
 
@@ -171,6 +164,31 @@ def test_repeat_runs_bit_identical():
     b = api.run(Xd, Yd, 1000, 3, "ed", "bf16r")
     assert torch.equal(a["perm_stats"], b["perm_stats"])
     assert a["statistic"] == b["statistic"] and a["threshold"] == b["threshold"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
+def test_graph_replay_with_new_inputs(prec):
+    """A shape run again replays a captured graph with this call's pointers, seed and gamma:
+    new data, seeds and kinds on the same shape must still match the oracle, and a replay
+    of the first call's inputs must reproduce it bit for bit."""
+    nx, ny, p, B = 210, 150, 33, 600
+    say("graph replay", prec)
+    runs = []
+    for rep, (ds, seed, kind) in enumerate([(31, 5, "ed"), (32, 6, "mmd"), (33, 7, "ed"),
+                                            (31, 5, "ed")]):
+        X, Y = _data(nx, ny, p, ds, prec, 0.2)
+        if prec == "bf16r":
+            X, Y = bf16_exact_pair(X, Y)  # p < 64: data the form represents exactly
+        g = api.run(_dev(X, prec), _dev(Y, prec), B, seed, kind, prec, 1.0 / p)
+        torch.cuda.synchronize()
+        runs.append(g)
+        if rep in (1, 2):
+            o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, seed, KIND[kind],
+                                1.0 / p)
+            compare_run(g, o, prec, "replay %d %s" % (rep, prec))
+    assert torch.equal(runs[0]["perm_stats"], runs[3]["perm_stats"])
+    assert runs[0]["statistic"] == runs[3]["statistic"]
+    assert runs[0]["count_ge"] == runs[3]["count_ge"]
 
 
 def test_batch_equals_alone():
