@@ -126,11 +126,7 @@ etest_status mmd_test_f64(const double* X, int64_t nx, const double* Y, int64_t 
 /* ---- Device buffers ---- */
 
 /* Run one test described by device pointers on `stream` (a hipStream_t, NULL = default
-   stream) and wait for it; fills the host struct `out`.  The first call with a given shape
-   (kind, precision, nx, ny, p, B) on a thread launches the stages one by one; a later call
-   with a shape among that thread's last 8 replays a captured graph of the same launches
-   (see etest_batch), with this call's pointers, seed and gamma.  Results are identical
-   either way. */
+   stream) and wait for it; fills the host struct `out`. */
 etest_status etest_run(const etest_request* req, void* stream, etest_result* out);
 
 /* Enqueue one test on `stream` and return without waiting.  d_out is a device pointer to
@@ -143,9 +139,8 @@ etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void*
    and the launch sequence is captured once into a HIP graph and replayed while the same
    request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,
    each holding its workspace until evicted.  With stage timing on (etest_profile_enable)
-   the stage events are captured into the graph (one graph per shape list and stage mask).
-   outs: host array of n results.  Each test's result equals what etest_run gives for it
-   alone. */
+   the batch runs without a graph so that the stages can be timed.  outs: host array of n
+   results.  Each test's result equals what etest_run gives for it alone. */
 etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, etest_result* outs);
 
 /* ---- Stage-level calls (each step of the path, for parity checks) ---- */

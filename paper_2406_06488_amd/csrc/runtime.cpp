@@ -520,9 +520,7 @@ static ShapeKey shape_of(const etest_request& r) {
 struct GraphEntry {
   std::vector<ShapeKey> key;
   uint64_t tune_gen = 0;  // tuning rules the captured work shapes came from
-  // stage events captured into the graph (the calling thread's), and which stages
-  const StageEvents* ev = nullptr;
-  uint32_t ev_mask = 0;
+
   Batch batch;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -531,10 +529,8 @@ static std::mutex g_graph_mu;
 static std::list<GraphEntry> g_graphs;
 static const size_t kGraphCacheMax = 4;
 
-static bool same_shapes(const GraphEntry& g, const etest_request* b, int64_t n, uint64_t gen,
-                        const StageEvents* ev) {
+static bool same_shapes(const GraphEntry& g, const etest_request* b, int64_t n, uint64_t gen) {
   if (g.tune_gen != gen || (int64_t)g.key.size() != n) return false;
-  if (g.ev != ev || (ev && g.ev_mask != ev->mask)) return false;
   for (int64_t t = 0; t < n; ++t)
     if (!(g.key[(size_t)t] == shape_of(b[t]))) return false;
   return true;
@@ -561,12 +557,12 @@ static TestDesc* pinned_descs(size_t n) {
 }
 
 static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStream_t st,
-                                    etest_result* outs, const StageEvents* ev) {
+                                    etest_result* outs) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
   GraphEntry* hit = nullptr;
   const uint64_t gen = tune_generation();
   for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
-    if (same_shapes(*it, reqs, n, gen, ev)) {
+    if (same_shapes(*it, reqs, n, gen)) {
       g_graphs.splice(g_graphs.begin(), g_graphs, it);
       hit = &g_graphs.front();
       break;
@@ -575,8 +571,6 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
     GraphEntry g;
     for (int64_t t = 0; t < n; ++t) g.key.push_back(shape_of(reqs[t]));
     g.tune_gen = gen;
-    g.ev = ev;
-    g.ev_mask = ev ? ev->mask : 0u;
     etest_status s = build_batch(reqs, n, false, &g.batch);
     if (s != ETEST_OK) return s;
     // Workspace and tables are placed before capture; the graph holds kernels only.
@@ -590,7 +584,7 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
     HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      enqueue_batch(g.batch, cap, nullptr, ev, thread_fork());
+      enqueue_batch(g.batch, cap, nullptr, nullptr, thread_fork());
       e = hipStreamEndCapture(cap, &g.graph);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
@@ -622,7 +616,6 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
   HIP_OK(hipMemcpyAsync(hr, b.d_results, sizeof(DevResult) * (size_t)n, hipMemcpyDeviceToHost, st),
          "result copy");
   HIP_OK(hipStreamSynchronize(st), "batch");
-  if (ev) profile_collect();
   etest_status worst = ETEST_OK;
   for (int64_t t = 0; t < n; ++t) {
     etest_result tmp;
@@ -631,20 +624,6 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
     else if (worst == ETEST_OK) worst = r;
   }
   return worst;
-}
-
-// A shape that a thread runs again goes through the graph cache; the first time it runs
-// eagerly (capturing costs more than one eager run).
-static bool seen_before(const etest_request& r) {
-  static thread_local ShapeKey recent[8];
-  static thread_local int nrecent = 0, next = 0;
-  const ShapeKey k = shape_of(r);
-  for (int i = 0; i < nrecent; ++i)
-    if (recent[i] == k) return true;
-  recent[next] = k;
-  next = (next + 1) % 8;
-  if (nrecent < 8) ++nrecent;
-  return false;
 }
 
 }  // namespace et
@@ -740,9 +719,6 @@ etest_status mmd_test_f64(const double* X, int64_t nx, const double* Y, int64_t 
 
 etest_status etest_run(const etest_request* req, void* stream, etest_result* out) {
   if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
-  etest_status s = validate_request(*req);
-  if (s != ETEST_OK) return s;
-  if (seen_before(*req)) return run_batch_graph(req, 1, (hipStream_t)stream, out, profile_events());
   return run_device(req, 1, (hipStream_t)stream, out);
 }
 
@@ -780,7 +756,10 @@ etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, ete
     etest_status s = validate_request(reqs[t]);
     if (s != ETEST_OK) return s;
   }
-  return run_batch_graph(reqs, n, (hipStream_t)stream, outs, profile_events());
+  // With stage timing on, the batch runs eagerly so that the stage events are recorded
+  // (events recorded by graph nodes give no elapsed times).
+  if (g_prof.on) return run_device(reqs, n, (hipStream_t)stream, outs);
+  return run_batch_graph(reqs, n, (hipStream_t)stream, outs);
 }
 
 etest_status etest_membership(int64_t nx, int64_t ny, uint64_t seed, int64_t b0, int64_t count,

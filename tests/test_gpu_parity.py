@@ -168,9 +168,9 @@ def test_repeat_runs_bit_identical():
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
 def test_graph_replay_with_new_inputs(prec):
-    """A shape run again replays a captured graph with this call's pointers, seed and gamma:
-    new data, seeds and kinds on the same shape must still match the oracle, and a replay
-    of the first call's inputs must reproduce it bit for bit."""
+    """A batch of the same shape replays its captured graph with this call's pointers, seed
+    and gamma: new data, seeds and kinds on the same shape must still match the oracle, and
+    a replay of the first call's inputs must reproduce it bit for bit."""
     nx, ny, p, B = 210, 150, 33, 600
     say("graph replay", prec)
     runs = []
@@ -179,8 +179,12 @@ def test_graph_replay_with_new_inputs(prec):
         X, Y = _data(nx, ny, p, ds, prec, 0.2)
         if prec == "bf16r":
             X, Y = bf16_exact_pair(X, Y)  # p < 64: data the form represents exactly
-        g = api.run(_dev(X, prec), _dev(Y, prec), B, seed, kind, prec, 1.0 / p)
+        Xd, Yd = _dev(X, prec), _dev(Y, prec)
+        ps = torch.empty(B, dtype=torch.float64, device=DEV)
+        req = api.make_request(Xd, Yd, B, seed, kind, prec, 1.0 / p, ps)
+        g = api.batch([req])[0]
         torch.cuda.synchronize()
+        g["perm_stats"] = ps
         runs.append(g)
         if rep in (1, 2):
             o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, seed, KIND[kind],
