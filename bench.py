@@ -99,10 +99,13 @@ def per_launch(prof):
     return {k: v[0] / v[1] for k, v in prof.items() if v[1] > 0}
 
 
-def roofline(stage_ms, tests, prec, workload=None):
+def roofline(stage_ms, tests, prec, workload=None, gram_tests=None):
     """Dominant kernel's algorithmic rate against its peak.  tests: list of (nx, ny, p, B)
-    processed per launch of each stage."""
-    gflops = sum(gram_flops(nx, ny, p) for nx, ny, p, B in tests)
+    whose resampled statistics one launch of the resampling stage computes; gram_tests: the
+    Gram products one launch of the block stage computes (default: the same tests; an ED
+    and an MMD test on the same data share one Gram)."""
+    gram_tests = tests if gram_tests is None else gram_tests
+    gflops = sum(gram_flops(nx, ny, p) for nx, ny, p, B in gram_tests)
     upd = sum(packed_pairs(nx, ny) * B for nx, ny, p, B in tests)
     if not stage_ms.get("blocks") or not stage_ms.get("resampling"):
         return None, None, None
@@ -227,16 +230,27 @@ def run_single(args):
     X, Y = wl.data()
     Xd, Yd = to_dev(X, Y, wl.prec)
 
-    def step(prec=wl.prec):
-        return [api.run(Xd, Yd, wl.B, wl.perm_seed, k, prec, wl.gamma()) for k in kinds]
+    if len(kinds) == 1:
+        def step(prec=wl.prec):
+            return [api.run(Xd, Yd, wl.B, wl.perm_seed, kinds[0], prec, wl.gamma())]
+    else:
+        # ED and MMD on the same data in one batch: they share staging and the Gram
+        import torch
+        outs = [torch.empty(wl.B, dtype=torch.float64, device="cuda:0") for _ in kinds]
+
+        def step(prec=wl.prec):
+            reqs = [api.make_request(Xd, Yd, wl.B, wl.perm_seed, k, prec, wl.gamma(), o)
+                    for k, o in zip(kinds, outs)]
+            return api.batch(reqs)
 
     elapsed, live, prof, res = timed(step, args.steps, args.warmup)
     stage = per_launch(prof)
     live_ms = {k: v for k, v in per_launch(live).items() if k in LIVE_STAGES}
     stage.update(live_ms)
     log("stage ms per test:", json.dumps({k: round(v, 4) for k, v in stage.items()}))
-    shape = [(wl.nx, wl.ny, wl.p, wl.B)]
-    roof, gram_tf, res_tf = roofline(stage, shape, wl.prec, wl.name)
+    gshape = [(wl.nx, wl.ny, wl.p, wl.B)]
+    shape = gshape * len(kinds)
+    roof, gram_tf, res_tf = roofline(stage, shape, wl.prec, wl.name, gshape)
     value = len(kinds) * wl.B * args.steps / elapsed
     line = base_line(args, wl.name, value, elapsed, args.steps,
                      {"f64": "f64", "f32": "f32", "bf16r": "bf16"}[wl.prec],
@@ -251,7 +265,7 @@ def run_single(args):
         e32, l32, p32, _ = timed(lambda: step("f32"), max(2, args.steps // 2), 1)
         s32 = per_launch(p32)
         s32.update({k: v for k, v in per_launch(l32).items() if k in LIVE_STAGES})
-        _, g32, r32 = roofline(s32, shape, "f32")
+        _, g32, r32 = roofline(s32, shape, "f32", None, gshape)
         line["f32_form"] = {"ms_per_step": 1e3 * e32 / max(2, args.steps // 2),
                             "gram_tflops": g32, "resampling_tflops": r32,
                             "stage_ms": {k: round(v, 5) for k, v in s32.items()}}

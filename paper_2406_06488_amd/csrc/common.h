@@ -25,6 +25,10 @@ namespace et {
 
 constexpr int TILE = 128;            // edge of a stored block tile
 constexpr int TILE_WORDS = TILE / 32;
+// Per stored tile: FP64 row sums [0, TILE), column sums of rows 0..63 [TILE, 2 TILE) and of
+// rows 64..127 [2 TILE, 3 TILE); two tile-max slots (one per row half).
+constexpr int TSUM_STRIDE = 3 * TILE;
+constexpr int TMAX_PER_TILE = 2;
 constexpr int NP = 256;              // split columns per resampling chunk
 constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
 constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
@@ -58,7 +62,7 @@ struct TestDesc {
   void* nrm;
   void* D;
   double* tsum;
-  float* tmax;       // [ntiles] largest |entry| of each stored tile
+  float* tmax;       // [ntiles][2] largest |entry| of each row half of each stored tile
   double* rsum;
   double* obs;       // [0..2] S_XX, S_YY, S_XY; [3] observed statistic; [4] R;
                      // [5] power-of-two scale of the fp16 planes
@@ -70,6 +74,14 @@ struct TestDesc {
   // flags[FLAG_COUNT..+1]: exceedance count (low half) and finished workgroups (high half)
   double* perm_out;
   DevResult* result;
+  // Shared block stage: an energy-distance test whose Gram also yields the Gaussian-kernel
+  // blocks of an MMD test on the same data (pD != nullptr) writes that test's D, tile sums,
+  // tile max and flags too.
+  void* pD;
+  double* ptsum;
+  float* ptmax;
+  int32_t* pflags;
+  double pgamma;
 };
 
 // Which test a flattened workgroup index belongs to: offs[t] <= bid < offs[t+1].

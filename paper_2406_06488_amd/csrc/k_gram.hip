@@ -41,13 +41,32 @@ __device__ inline const float* input_row_f32(const TestDesc& d, int i, int r) {
   return (const float*)d.Y + ((int64_t)(i - d.tx) * TILE + r) * d.p;
 }
 
-// d^2 -> stored block value; padding rows/columns hold 0.
-__device__ inline float block_value_f32(const TestDesc& d, const TileCtx& c, int r, int col,
+// d^2 -> stored block value (distance, or Gaussian kernel with bandwidth 1 / gamma);
+// padding rows/columns hold 0.
+__device__ inline float block_value_f32(int kind, double gamma, const TileCtx& c, int r, int col,
                                         float d2) {
   if (r >= c.rows_i || col >= c.rows_j) return 0.0f;
-  if (c.diag && r == col) return d.kind == KIND_ED ? 0.0f : 1.0f;
+  if (c.diag && r == col) return kind == KIND_ED ? 0.0f : 1.0f;
   d2 = fmaxf(d2, 0.0f);
-  return d.kind == KIND_ED ? sqrtf(d2) : expf((float)(-d.gamma) * d2);
+  return kind == KIND_ED ? sqrtf(d2) : expf((float)(-gamma) * d2);
+}
+
+// The block outputs one epilogue pass writes: the test's own, or those of the MMD test it
+// feeds (shared block stage).
+struct BlockOut {
+  int kind;
+  double gamma;
+  float* D;
+  double* tsum;
+  float* tmax;
+};
+__device__ inline BlockOut own_out(const TestDesc& d, int t) {
+  return BlockOut{d.kind, d.gamma, (float*)d.D + (int64_t)t * TILE * TILE,
+                  d.tsum + (int64_t)t * TSUM_STRIDE, d.tmax + (int64_t)t * TMAX_PER_TILE};
+}
+__device__ inline BlockOut partner_out(const TestDesc& d, int t) {
+  return BlockOut{KIND_MMD, d.pgamma, (float*)d.pD + (int64_t)t * TILE * TILE,
+                  d.ptsum + (int64_t)t * TSUM_STRIDE, d.ptmax + (int64_t)t * TMAX_PER_TILE};
 }
 
 // Epilogue through LDS, half a tile (64 rows) at a time so the workgroup needs at most
@@ -56,14 +75,96 @@ __device__ inline float block_value_f32(const TestDesc& d, const TileCtx& c, int
 // coalesced store of the half tile.  v[mb][nb][e] holds the block value of row
 // wm*64 + mb*32 + 8*(e/4) + 4*h + e%4, column wn*64 + nb*32 + lane%32.
 constexpr int HALF = TILE / 2;
-__device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, float* tl,
-                                       const f32x16 (&v)[2][2], int wm, int wn, int h, int lr) {
+// Entries (v) of a full tile -> block values of one output through LDS, half a tile at a
+// time: FP64 row sums (complete per half), column sums per half, coalesced store
+// and the tile max.  v[mb][nb][e] is the entry of row wm*64 + mb*32 + 8*(e/4) + 4*h + e%4,
+// column wn*64 + nb*32 + lr.
+template <bool TRANSFORM>
+__device__ inline void finish_tile_f32(const TileCtx& c, float* tl, const f32x16 (&v)[2][2],
+                                       int wm, int wn, int h, int lr, const BlockOut o) {
   __shared__ unsigned int tile_max_bits;
   const int tid = threadIdx.x;
-  float* D = (float*)d.D + (int64_t)c.t * TILE * TILE;
-  double colsum = 0.0;
   float vmax = 0.0f;
+  __syncthreads();
   if (tid == 0) tile_max_bits = 0u;
+  for (int half = 0; half < 2; ++half) {
+    __syncthreads();
+    if (wm == half) {
+      for (int mb = 0; mb < 2; ++mb)
+        for (int nb = 0; nb < 2; ++nb)
+          for (int e = 0; e < 16; ++e) {
+            const int r = mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);  // row within the half
+            const int col = wn * 64 + nb * 32 + lr;
+            // TRANSFORM: v holds squared distances; otherwise the block values already
+            tl[r * TILE_LDS + col] =
+                TRANSFORM ? block_value_f32(o.kind, o.gamma, c, half * HALF + r, col, v[mb][nb][e])
+                          : v[mb][nb][e];
+          }
+    }
+    __syncthreads();
+    if (tid < HALF) {
+      double s = 0.0;
+      for (int k = 0; k < TILE; ++k) {
+        const float x = tl[tid * TILE_LDS + k];
+        s += (double)x;
+        vmax = fmaxf(vmax, fabsf(x));
+      }
+      o.tsum[half * HALF + tid] = s;
+    } else if (tid >= TILE) {
+      const int col = tid - TILE;
+      double colsum = 0.0;
+      for (int k = 0; k < HALF; ++k) colsum += (double)tl[k * TILE_LDS + col];
+      o.tsum[TILE * (1 + half) + col] = colsum;
+    }
+    for (int e = tid; e < HALF * TILE; e += 256)
+      o.D[half * HALF * TILE + e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
+  }
+  // non-negative floats order like their bit patterns
+  if (tid < HALF) atomicMax(&tile_max_bits, __float_as_uint(vmax));
+  __syncthreads();
+  if (tid == 0) {
+    o.tmax[0] = __uint_as_float(tile_max_bits);
+    o.tmax[1] = 0.0f;
+  }
+}
+
+// Squared distances (v) of a full tile -> block values of the test's own output and, with
+// has1, of the MMD test it feeds.  The squared distances are staged in LDS once per half
+// tile and each output is derived from them as it is read, so v is not held across two
+// passes.
+__device__ inline void finish_tile_dual(const TileCtx& c, float* tl, const f32x16 (&v)[2][2],
+                                        int wm, int wn, int h, int lr, const BlockOut o0,
+                                        const BlockOut o1, const bool has1) {
+  __shared__ unsigned int tile_max_bits[2];
+  const int tid = threadIdx.x;
+  float vmax0 = 0.0f, vmax1 = 0.0f;
+  // row sums, column sums and store of one output from the squared distances in tl
+  auto emit = [&](const BlockOut o, int half, float& vmax) {
+    if (tid < HALF) {
+      const int r = half * HALF + tid;
+      double s = 0.0;
+      for (int k = 0; k < TILE; ++k) {
+        const float x = block_value_f32(o.kind, o.gamma, c, r, k, tl[tid * TILE_LDS + k]);
+        s += (double)x;
+        vmax = fmaxf(vmax, fabsf(x));
+      }
+      o.tsum[r] = s;
+    } else if (tid >= TILE) {
+      const int col = tid - TILE;
+      double colsum = 0.0;
+      for (int k = 0; k < HALF; ++k)
+        colsum += (double)block_value_f32(o.kind, o.gamma, c, half * HALF + k, col,
+                                          tl[k * TILE_LDS + col]);
+      o.tsum[TILE * (1 + half) + col] = colsum;
+    }
+    for (int e = tid; e < HALF * TILE; e += 256) {
+      const int rl = e / TILE, col = e % TILE;
+      o.D[half * HALF * TILE + e] =
+          block_value_f32(o.kind, o.gamma, c, half * HALF + rl, col, tl[rl * TILE_LDS + col]);
+    }
+  };
+  __syncthreads();
+  if (tid < 2) tile_max_bits[tid] = 0u;
   for (int half = 0; half < 2; ++half) {
     __syncthreads();
     if (wm == half) {
@@ -75,66 +176,85 @@ __device__ inline void finish_tile_f32(const TestDesc& d, const TileCtx& c, floa
           }
     }
     __syncthreads();
-    if (tid < HALF) {
-      double s = 0.0;
-      for (int k = 0; k < TILE; ++k) {
-        const float x = tl[tid * TILE_LDS + k];
-        s += (double)x;
-        vmax = fmaxf(vmax, fabsf(x));
-      }
-      d.tsum[(int64_t)c.t * 2 * TILE + half * HALF + tid] = s;
-    } else if (tid >= TILE) {
-      const int col = tid - TILE;
-      for (int k = 0; k < HALF; ++k) colsum += (double)tl[k * TILE_LDS + col];
-    }
-    for (int e = tid; e < HALF * TILE; e += 256)
-      D[half * HALF * TILE + e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
+    emit(o0, half, vmax0);
+    if (has1) emit(o1, half, vmax1);
   }
-  if (tid >= TILE) d.tsum[(int64_t)c.t * 2 * TILE + TILE + (tid - TILE)] = colsum;
   // non-negative floats order like their bit patterns
-  if (tid < HALF) atomicMax(&tile_max_bits, __float_as_uint(vmax));
+  if (tid < HALF) {
+    atomicMax(&tile_max_bits[0], __float_as_uint(vmax0));
+    if (has1) atomicMax(&tile_max_bits[1], __float_as_uint(vmax1));
+  }
   __syncthreads();
-  if (tid == 0) d.tmax[c.t] = __uint_as_float(tile_max_bits);
+  if (tid == 0) {
+    o0.tmax[0] = __uint_as_float(tile_max_bits[0]);
+    o0.tmax[1] = 0.0f;
+    if (has1) {
+      o1.tmax[0] = __uint_as_float(tile_max_bits[1]);
+      o1.tmax[1] = 0.0f;
+    }
+  }
 }
 
-// Gram entries -> block values in place.  d^2 = |w_a|^2 + |w_b|^2 - 2 g; pairs with
+// Gram entry -> squared distance.  d^2 = |w_a|^2 + |w_b|^2 - 2 g; pairs with
 // d^2 < 1e-3 (|w_a|^2 + |w_b|^2), where that difference has cancelled most of its
 // digits, are recomputed as a direct FP32 difference of the input rows.
+__device__ inline float gram_d2(const TestDesc& d, const TileCtx& c, int r, int col, float g,
+                                float nr, float nc, int* refined) {
+  float d2 = nr + nc - 2.0f * g;
+  if (d.refine && r < c.rows_i && col < c.rows_j && !(c.diag && r == col) &&
+      d2 < 1e-3f * (nr + nc)) {
+    const float* xa = input_row_f32(d, c.i, r);
+    const float* xb = input_row_f32(d, c.j, col);
+    float s = 0.0f;
+    for (int k = 0; k < d.p; ++k) {
+      const float df = xa[k] - xb[k];
+      s = fmaf(df, df, s);
+    }
+    d2 = s;
+    ++*refined;
+  }
+  return d2;
+}
+
+__device__ inline void add_refined(const TestDesc& d, int refined) {
+  if (!refined) return;
+  atomicAdd(&d.flags[1], refined);
+  if (d.pflags) atomicAdd(&d.pflags[1], refined);
+}
+
+// Gram entries of a full-tile workgroup (2 x 2 waves of 64 x 64) -> squared distances
+// (VALUES false) or the test's own block values (VALUES true), in place.
+template <bool VALUES>
 __device__ inline void gram_epilogue(const TestDesc& d, const TileCtx& c, f32x16 (&acc)[2][2],
                                      int wm, int wn, int h, int lr) {
+  // the tile's 128 row norms and 128 column norms, staged once instead of two global
+  // loads per entry
+  __shared__ float snorm[2 * TILE];
+  const int tid = threadIdx.x;
+  {
+    const float* nrm = (const float*)d.nrm;
+    snorm[tid] = nrm[(int64_t)(tid < TILE ? c.i : c.j) * TILE + (tid & (TILE - 1))];
+  }
   __syncthreads();
-  const float* nrm = (const float*)d.nrm;
   int refined = 0;
   for (int mb = 0; mb < 2; ++mb)
     for (int nb = 0; nb < 2; ++nb) {
       const int col = wn * 64 + nb * 32 + lr;
-      const float nc = nrm[(int64_t)c.j * TILE + col];
+      const float nc = snorm[TILE + col];
       for (int e = 0; e < 16; ++e) {
         const int r = wm * 64 + mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-        const float nr = nrm[(int64_t)c.i * TILE + r];
-        float d2 = nr + nc - 2.0f * acc[mb][nb][e];
-        if (d.refine && r < c.rows_i && col < c.rows_j && !(c.diag && r == col) &&
-            d2 < 1e-3f * (nr + nc)) {
-          const float* xa = input_row_f32(d, c.i, r);
-          const float* xb = input_row_f32(d, c.j, col);
-          float s = 0.0f;
-          for (int k = 0; k < d.p; ++k) {
-            const float df = xa[k] - xb[k];
-            s = fmaf(df, df, s);
-          }
-          d2 = s;
-          ++refined;
-        }
-        acc[mb][nb][e] = block_value_f32(d, c, r, col, d2);
+        const float d2 = gram_d2(d, c, r, col, acc[mb][nb][e], snorm[r], nc, &refined);
+        acc[mb][nb][e] = VALUES ? block_value_f32(d.kind, d.gamma, c, r, col, d2) : d2;
       }
     }
-  if (refined) atomicAdd(&d.flags[1], refined);
+  add_refined(d, refined);
 }
 
 // ---------------------------------------------------------------- FP32 MFMA
 // 4 waves as 2 x 2, each 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x2_f32.
 // Three resident workgroups per CU (register budget <= 168 per lane): 768 slots, so a
 // 2000 + 2000 test's 528 tiles run in a single round.
+template <bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_gram_f32(const TestDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ offs, int ntests) {
@@ -207,13 +327,22 @@ k_gram_f32(const TestDesc* __restrict__ descs,
                                                                0, 0, 0);
     }
   }
-  gram_epilogue(d, c, acc, wm, wn, h, lr);
-  finish_tile_f32(d, c, smem, acc, wm, wn, h, lr);
+  // DUAL: launches that hold a test feeding an MMD test keep the squared distances for two
+  // outputs; plain launches turn them into block values at once
+  if (DUAL) {
+    gram_epilogue<false>(d, c, acc, wm, wn, h, lr);
+    finish_tile_dual(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
+                     d.pD != nullptr);
+  } else {
+    gram_epilogue<true>(d, c, acc, wm, wn, h, lr);
+    finish_tile_f32<false>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t));
+  }
 }
 
 // ---------------------------------------------------------------- BF16 MFMA
 // Same arrangement with v_mfma_f32_32x32x16_bf16; pairs whose Gram-based d^2
 // falls below 1e-3 of the norm sum are recomputed from the FP32 input rows.
+template <bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_gram_bf16(const TestDesc* __restrict__ descs,
                                                    const int64_t* __restrict__ offs, int ntests) {
@@ -282,8 +411,16 @@ k_gram_bf16(const TestDesc* __restrict__ descs,
               __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
     }
   }
-  gram_epilogue(d, c, acc, wm, wn, h, lr);
-  finish_tile_f32(d, c, smem, acc, wm, wn, h, lr);
+  // DUAL: launches that hold a test feeding an MMD test keep the squared distances for two
+  // outputs; plain launches turn them into block values at once
+  if (DUAL) {
+    gram_epilogue<false>(d, c, acc, wm, wn, h, lr);
+    finish_tile_dual(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
+                     d.pD != nullptr);
+  } else {
+    gram_epilogue<true>(d, c, acc, wm, wn, h, lr);
+    finish_tile_f32<false>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t));
+  }
 }
 
 // ---------------------------------------------------------------- FP64 direct
@@ -345,23 +482,29 @@ __global__ void __launch_bounds__(256) k_dist_f64(const TestDesc* __restrict__ d
   double s = 0.0;
   if (tid < TILE) {
     for (int q = 0; q < 16; ++q) s += rp[tid * 16 + q];
-    d.tsum[(int64_t)c.t * 2 * TILE + tid] = s;
+    d.tsum[(int64_t)c.t * TSUM_STRIDE + tid] = s;
   } else {
     const int col = tid - TILE;
     for (int q = 0; q < 16; ++q) s += cp[q * TILE + col];
-    d.tsum[(int64_t)c.t * 2 * TILE + TILE + col] = s;
+    d.tsum[(int64_t)c.t * TSUM_STRIDE + TILE + col] = s;  // all 128 rows in one slot
+    d.tsum[(int64_t)c.t * TSUM_STRIDE + 2 * TILE + col] = 0.0;
   }
 }
 
 void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d,
-                 const int64_t* offs, int n) {
+                 const int64_t* offs, int n, bool dual) {
   if (blocks <= 0) return;
+  const dim3 g((unsigned)blocks), b(256);
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(k_dist_f64, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+    hipLaunchKernelGGL(k_dist_f64, g, b, 0, st, d, offs, n);
+  else if (prec == PREC_F32 && dual)
+    hipLaunchKernelGGL(k_gram_f32<true>, g, b, 0, st, d, offs, n);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL(k_gram_f32, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+    hipLaunchKernelGGL(k_gram_f32<false>, g, b, 0, st, d, offs, n);
+  else if (dual)
+    hipLaunchKernelGGL(k_gram_bf16<true>, g, b, 0, st, d, offs, n);
   else
-    hipLaunchKernelGGL(k_gram_bf16, dim3((unsigned)blocks), dim3(256), 0, st, d, offs, n);
+    hipLaunchKernelGGL(k_gram_bf16<false>, g, b, 0, st, d, offs, n);
 }
 
 }  // namespace et

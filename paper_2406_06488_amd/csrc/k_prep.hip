@@ -155,7 +155,10 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
     nrm = wave_sum(nrm);
     if (lane == 0) ((float*)d.nrm)[pos] = (float)nrm;
   }
-  if (bad) atomicOr(&d.flags[0], 1);
+  if (bad) {
+    atomicOr(&d.flags[0], 1);
+    if (d.pflags) atomicOr(&d.pflags[0], 1);  // the MMD test fed by this staging
+  }
 }
 
 // Clear the per-test flag words (a kernel rather than a memset so that the

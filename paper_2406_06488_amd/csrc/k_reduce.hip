@@ -25,14 +25,20 @@ __global__ void __launch_bounds__(64) k_rowsum(const TestDesc* __restrict__ desc
   const double* ts = d.tsum;
   const bool isx = i < d.tx;
   double s = 0.0;
+  // row sums of tile (i, j); column sums (two row halves) of tile (j, i)
+  auto rowsum = [&](int j) { return ts[(int64_t)tile_index(i, j, d.nt) * TSUM_STRIDE + r]; };
+  auto colsum = [&](int j) {
+    const double* t = ts + (int64_t)tile_index(j, i, d.nt) * TSUM_STRIDE;
+    return t[TILE + r] + t[2 * TILE + r];
+  };
   if (!cross) {
     const int b0 = isx ? 0 : d.tx, b1 = isx ? d.tx : d.nt;  // own block's tile range
-    for (int j = b0; j < i; ++j) s += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
-    for (int j = i; j < b1; ++j) s += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
+    for (int j = b0; j < i; ++j) s += colsum(j);
+    for (int j = i; j < b1; ++j) s += rowsum(j);
   } else if (isx) {
-    for (int j = d.tx; j < d.nt; ++j) s += ts[(int64_t)tile_index(i, j, d.nt) * 2 * TILE + r];
+    for (int j = d.tx; j < d.nt; ++j) s += rowsum(j);
   } else {
-    for (int j = 0; j < d.tx; ++j) s += ts[(int64_t)tile_index(j, i, d.nt) * 2 * TILE + TILE + r];
+    for (int j = 0; j < d.tx; ++j) s += colsum(j);
   }
   d.rsum[pos * 2 + (cross ? 1 : 0)] = s;
 }
@@ -96,7 +102,7 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
   __shared__ float mx[256];
   float m = 0.0f;
   if (d.prec != PREC_F64)
-    for (int t = tid; t < d.ntiles; t += 256) m = fmaxf(m, d.tmax[t]);
+    for (int t = tid; t < d.ntiles * TMAX_PER_TILE; t += 256) m = fmaxf(m, d.tmax[t]);
   mx[tid] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {

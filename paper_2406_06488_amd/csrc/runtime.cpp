@@ -135,8 +135,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   sz[B_W] = (size_t)npad * d.p_pad * el_w;
   sz[B_NRM] = (size_t)npad * (f64 ? 8 : 4);
   sz[B_D] = (size_t)d.ntiles * TILE * TILE * el_d;
-  sz[B_TSUM] = (size_t)d.ntiles * 2 * TILE * 8;
-  sz[B_TMAX] = (size_t)d.ntiles * 4;
+  sz[B_TSUM] = (size_t)d.ntiles * TSUM_STRIDE * 8;
+  sz[B_TMAX] = (size_t)d.ntiles * TMAX_PER_TILE * 4;
   sz[B_RSUM] = (size_t)npad * 2 * 8;
   sz[B_OBS] = 8 * 8;
   sz[B_PLANES] = f64 ? (size_t)d.ntiles * TILE * TILE * 8
@@ -176,6 +176,48 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   return P;
 }
 
+Pairing pair_tests(const etest_request* reqs, int64_t n) {
+  Pairing P;
+  P.partner.assign((size_t)n, -1);
+  P.share_z.assign((size_t)n, 0);
+  std::vector<char> fed((size_t)n, 0);
+  for (int64_t s = 0; s < n; ++s) {
+    const etest_request& a = reqs[s];
+    if (a.kind != ETEST_ED || a.prec == ETEST_PREC_F64) continue;
+    for (int64_t u = 0; u < n; ++u) {
+      const etest_request& m = reqs[u];
+      if (fed[(size_t)u] || m.kind != ETEST_MMD || m.prec != a.prec || m.X != a.X ||
+          m.Y != a.Y || m.nx != a.nx || m.ny != a.ny || m.p != a.p)
+        continue;
+      P.partner[(size_t)s] = (int)u;
+      P.share_z[(size_t)s] = (char)(m.seed == a.seed && m.B == a.B);
+      fed[(size_t)u] = 1;
+      break;
+    }
+  }
+  return P;
+}
+
+void link_partners(TestDesc* descs, const Pairing& pairing) {
+  for (size_t s = 0; s < pairing.partner.size(); ++s) {
+    TestDesc& a = descs[s];
+    a.pD = nullptr;
+    a.ptsum = nullptr;
+    a.ptmax = nullptr;
+    a.pflags = nullptr;
+    a.pgamma = 0.0;
+    const int u = pairing.partner[s];
+    if (u < 0) continue;
+    TestDesc& m = descs[u];
+    a.pD = m.D;
+    a.ptsum = m.tsum;
+    a.ptmax = m.tmax;
+    a.pflags = m.flags;
+    a.pgamma = m.gamma;
+    if (pairing.share_z[s]) m.Z = a.Z;  // identical split streams: one copy
+  }
+}
+
 etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_perm, Batch* b) {
   b->plans.clear();
   b->plans.reserve((size_t)n);
@@ -190,6 +232,18 @@ etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_per
       P.internal_perm = true;
     }
     b->plans.push_back(P);
+  }
+  // an MMD test fed by an ED test skips its own staging and Gram (and its split stream
+  // when it is the same one)
+  const Pairing pairing = pair_tests(reqs, n);
+  for (int64_t s = 0; s < n; ++s) {
+    const int u = pairing.partner[(size_t)s];
+    b->plans[(size_t)s].partner = u;
+    b->plans[(size_t)s].share_z = pairing.share_z[(size_t)s] != 0;
+    if (u < 0) continue;
+    for (int k : {S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16})
+      b->plans[(size_t)u].wg[k] = 0;
+    if (pairing.share_z[(size_t)s]) b->plans[(size_t)u].wg[S_MEMBER] = 0;
   }
   return ETEST_OK;
 }
@@ -243,13 +297,20 @@ etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered) {
   b->d_results = (DevResult*)(w + desc_bytes + offs_bytes);
   b->descs.resize((size_t)n);
   b->offs.assign((size_t)S_COUNT * (size_t)(n + 1), 0);
+  Pairing pairing;
+  pairing.partner.resize((size_t)n);
+  pairing.share_z.resize((size_t)n);
   for (int t = 0; t < n; ++t) {
     TestPlan& P = b->plans[(size_t)t];
     assign_pointers(P, w + base[(size_t)t], b->d_results + t);
     b->descs[(size_t)t] = P.d;
+    pairing.partner[(size_t)t] = P.partner;
+    pairing.share_z[(size_t)t] = P.share_z ? 1 : 0;
     for (int s = 0; s < S_COUNT; ++s)
       b->offs[(size_t)s * (n + 1) + t + 1] = b->offs[(size_t)s * (n + 1) + t] + P.wg[s];
   }
+  link_partners(b->descs.data(), pairing);
+  for (int t = 0; t < n; ++t) b->plans[(size_t)t].d = b->descs[(size_t)t];
   e = hipMemcpyAsync(b->d_descs, b->descs.data(), sizeof(TestDesc) * (size_t)n,
                      hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
@@ -299,9 +360,11 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   end(2, ms);
   if (fork) (void)hipEventRecord(fork->done, ms);
   begin(1, st);
-  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n);
-  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n);
-  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n);
+  bool dual = false;
+  for (const TestPlan& P : b.plans) dual = dual || P.partner >= 0;
+  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n, dual);
+  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n, dual);
+  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n, dual);
   end(1, st);
   begin(3, st);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), n);
@@ -509,12 +572,16 @@ static etest_status run_host(int kind, int prec, const void* X, int64_t nx, cons
 struct ShapeKey {
   int32_t kind, prec;
   int64_t nx, ny, p, B;
+  int partner;  // shared block stage (pair_tests), which changes the launch sequence
+  int share_z;
   bool operator==(const ShapeKey& o) const {
-    return kind == o.kind && prec == o.prec && nx == o.nx && ny == o.ny && p == o.p && B == o.B;
+    return kind == o.kind && prec == o.prec && nx == o.nx && ny == o.ny && p == o.p &&
+           B == o.B && partner == o.partner && share_z == o.share_z;
   }
 };
-static ShapeKey shape_of(const etest_request& r) {
-  return ShapeKey{r.kind, r.prec, r.nx, r.ny, r.p, r.B};
+static ShapeKey shape_of(const etest_request& r, const Pairing& pg, int64_t t) {
+  return ShapeKey{r.kind, r.prec, r.nx, r.ny, r.p, r.B, pg.partner[(size_t)t],
+                  (int)pg.share_z[(size_t)t]};
 }
 
 struct GraphEntry {
@@ -529,10 +596,11 @@ static std::mutex g_graph_mu;
 static std::list<GraphEntry> g_graphs;
 static const size_t kGraphCacheMax = 4;
 
-static bool same_shapes(const GraphEntry& g, const etest_request* b, int64_t n, uint64_t gen) {
+static bool same_shapes(const GraphEntry& g, const etest_request* b, int64_t n, uint64_t gen,
+                        const Pairing& pg) {
   if (g.tune_gen != gen || (int64_t)g.key.size() != n) return false;
   for (int64_t t = 0; t < n; ++t)
-    if (!(g.key[(size_t)t] == shape_of(b[t]))) return false;
+    if (!(g.key[(size_t)t] == shape_of(b[t], pg, t))) return false;
   return true;
 }
 
@@ -561,15 +629,16 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
   std::lock_guard<std::mutex> lk(g_graph_mu);
   GraphEntry* hit = nullptr;
   const uint64_t gen = tune_generation();
+  const Pairing pairing = pair_tests(reqs, n);
   for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
-    if (same_shapes(*it, reqs, n, gen)) {
+    if (same_shapes(*it, reqs, n, gen, pairing)) {
       g_graphs.splice(g_graphs.begin(), g_graphs, it);
       hit = &g_graphs.front();
       break;
     }
   if (!hit) {
     GraphEntry g;
-    for (int64_t t = 0; t < n; ++t) g.key.push_back(shape_of(reqs[t]));
+    for (int64_t t = 0; t < n; ++t) g.key.push_back(shape_of(reqs[t], pairing, t));
     g.tune_gen = gen;
     etest_status s = build_batch(reqs, n, false, &g.batch);
     if (s != ETEST_OK) return s;
@@ -610,6 +679,7 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
     assign_pointers(P, (char*)b.ws + b.base[(size_t)t], b.d_results + t);
     hd[t] = P.d;
   }
+  link_partners(hd, pairing);
   HIP_OK(hipMemcpyAsync(b.d_descs, hd, sizeof(TestDesc) * (size_t)n, hipMemcpyHostToDevice, st),
          "descriptor copy");
   HIP_OK(hipGraphLaunch(hit->exec, st), "graph launch");

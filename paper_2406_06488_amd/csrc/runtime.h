@@ -16,7 +16,7 @@ void launch_colpart(int64_t blocks, hipStream_t st, const TestDesc* d, const int
 void launch_colmean(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_stage(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
-                 int n);
+                 int n, bool dual = false);
 void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
 void launch_center(bool f64, int64_t blocks, hipStream_t st, const TestDesc* d,
@@ -53,6 +53,8 @@ struct TestPlan {
   size_t off[16] = {};       // offsets of its buffers inside its region
   size_t size[16] = {};      // their sizes in bytes
   bool internal_perm = false;  // per-split output lives in the region (off[B_PERMOUT])
+  int partner = -1;          // ED test: index of the MMD test whose blocks its Gram writes
+  bool share_z = false;      // ... and whose split stream it provides
   int64_t wg[S_COUNT] = {};  // workgroups per launch slot
 };
 
@@ -77,6 +79,16 @@ struct Batch {
 
 // Point a plan's descriptor at its buffers inside a device region.
 void assign_pointers(TestPlan& P, char* region, DevResult* result);
+// ED / MMD pairs of a request list that share staging and Gram: partner[s] = t when the
+// ED test s feeds the MMD test t (same X, Y pointers, shapes and precision), else -1.
+// share_z[s]: the pair also has the same seed and B, so t reads s's split stream.
+struct Pairing {
+  std::vector<int> partner;
+  std::vector<char> share_z;
+};
+Pairing pair_tests(const etest_request* reqs, int64_t n);
+// Fill the ED tests' pointers to their partners' buffers (descriptors already placed).
+void link_partners(TestDesc* descs, const Pairing& pairing);
 void init_pool_once();
 
 // Build plans + layout (host only).  extra_perm: allocate internal perm-stat

@@ -13,7 +13,7 @@ void launch_clear_flags(hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_colpart(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_colmean(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_stage(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
-void launch_gram(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_gram(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int, bool) {}
 void launch_rowsum(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_observed(hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_center(bool, int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}

@@ -216,6 +216,32 @@ def test_batch_equals_alone():
             assert torch.equal(keep[3 * t + 2], alone[t]["perm_stats"]), (rep, t)
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16r"])
+def test_shared_block_stage_equals_alone(prec):
+    """An ED and an MMD test on the same X, Y in one batch share staging and Gram (the ED
+    test's epilogue writes the kernel blocks too), and with the same seed and B also the
+    split stream; each result must equal its run alone, bit for bit, also when the MMD
+    test comes first."""
+    X, Y = _data(260, 190, 70, 41, prec, 0.2)
+    X2, Y2 = _data(260, 190, 70, 42, prec, 0.2)
+    Xd, Yd, X2d, Y2d = _dev(X, prec), _dev(Y, prec), _dev(X2, prec), _dev(Y2, prec)
+    specs = [("mmd", Xd, Yd, 11), ("ed", Xd, Yd, 12), ("mmd", X2d, Y2d, 13), ("ed", X2d, Y2d, 13)]
+    B, gamma = 700, 1.0 / 70
+    reqs, outs_ps, alone = [], [], []
+    for kind, A, Bm, seed in specs:
+        ps = torch.zeros(B, dtype=torch.float64, device=DEV)
+        outs_ps.append(ps)
+        reqs.append(api.make_request(A, Bm, B, seed, kind, prec, gamma, ps))
+        alone.append(api.run(A, Bm, B, seed, kind, prec, gamma))
+    for rep in range(2):
+        outs = api.batch(reqs)
+        torch.cuda.synchronize()
+        for t in range(len(specs)):
+            for k in ("statistic", "threshold", "count_ge", "p_value", "n_refined"):
+                assert outs[t][k] == alone[t][k], (rep, t, k)
+            assert torch.equal(outs_ps[t], alone[t]["perm_stats"]), (rep, t)
+
+
 def test_enumeration_through_supplied_splits():
     """nx = ny = 5: all 252 splits evaluated on the GPU equal the oracle's table; the
     identity equals the threshold and its complement ties with it."""
