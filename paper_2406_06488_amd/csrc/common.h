@@ -84,6 +84,21 @@ struct TestDesc {
   double pgamma;
 };
 
+// Workgroups of a launch are dealt to the 8 XCDs in turn (workgroup b on XCD b % 8), and
+// each XCD has its own L2.  xcd_grouped renumbers them so that every XCD works through
+// runs of XCD_GROUP consecutive units of the flattened work list (neighbouring units read
+// the same operand tiles and then share an L2), while the runs themselves are still dealt
+// to the XCDs in turn, which keeps their loads balanced.  A bijection on [0, grid): the
+// tail that does not fill a whole round of 8 runs keeps its order.
+constexpr int NUM_XCD = 8;
+constexpr int XCD_GROUP = 8;
+__device__ inline int64_t xcd_grouped(int64_t bid, int64_t grid) {
+  const int64_t round = (int64_t)NUM_XCD * XCD_GROUP;
+  if (bid >= grid / round * round) return bid;
+  const int64_t x = bid % NUM_XCD, k = bid / NUM_XCD;
+  return ((k / XCD_GROUP) * NUM_XCD + x) * XCD_GROUP + k % XCD_GROUP;
+}
+
 // Which test a flattened workgroup index belongs to: offs[t] <= bid < offs[t+1].
 __device__ inline int find_test(const int64_t* __restrict__ offs, int ntests, int64_t bid) {
   int lo = 0, hi = ntests - 1;

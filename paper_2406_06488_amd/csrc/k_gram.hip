@@ -260,9 +260,10 @@ k_gram_f32(const TestDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ offs, int ntests) {
   __shared__ float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F32 ? HALF * TILE_LDS
                                                                   : 2 * TILE * LDS_ROW_F32];
-  const int ti = find_test(offs, ntests, blockIdx.x);
+  const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
+  const int ti = find_test(offs, ntests, bid);
   const TestDesc d = descs[ti];
-  const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
+  const TileCtx c = tile_ctx(d, bid - offs[ti]);
   const float* Wa = (const float*)d.W + (int64_t)c.i * TILE * d.p_pad;
   const float* Wb = (const float*)d.W + (int64_t)c.j * TILE * d.p_pad;
   float* As = smem;
@@ -348,9 +349,10 @@ k_gram_bf16(const TestDesc* __restrict__ descs,
                                                    const int64_t* __restrict__ offs, int ntests) {
   __shared__ float smem[HALF * TILE_LDS > TILE * LDS_ROW_BF16 ? HALF * TILE_LDS
                                                               : TILE * LDS_ROW_BF16];
-  const int ti = find_test(offs, ntests, blockIdx.x);
+  const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
+  const int ti = find_test(offs, ntests, bid);
   const TestDesc d = descs[ti];
-  const TileCtx c = tile_ctx(d, blockIdx.x - offs[ti]);
+  const TileCtx c = tile_ctx(d, bid - offs[ti]);
   const uint16_t* Wa = (const uint16_t*)d.W + (int64_t)c.i * TILE * d.p_pad;
   const uint16_t* Wb = (const uint16_t*)d.W + (int64_t)c.j * TILE * d.p_pad;
   uint16_t* As = (uint16_t*)smem;

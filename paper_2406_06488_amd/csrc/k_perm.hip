@@ -78,9 +78,10 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
   constexpr int ZW = TILE_WORDS * 2 * NP / 4;  // 16-byte groups of membership words (512)
   constexpr int BUF = S * FR + ZW;            // 16-byte slots per buffer
   __shared__ uint4 lds[2 * BUF];
-  const int ti = find_test(offs, ntests, blockIdx.x);
+  const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
+  const int ti = find_test(offs, ntests, bid);
   const TestDesc d = descs[ti];
-  const PermUnit u = perm_unit(d, ti, blockIdx.x - offs[ti], pcr);
+  const PermUnit u = perm_unit(d, ti, bid - offs[ti], pcr);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, lr = lane & 31;
   const int64_t BP = d.B_pad;
   const int nch = u.ce - u.cb;  // 1 or 2
