@@ -32,6 +32,14 @@ __device__ inline double center_value(const TestDesc& d, int i, int j, int r, in
   return x;
 }
 
+// FP64 -> FP32, kept as a separate step: folded into the fp16 conversion that follows it,
+// it would become one FP64 -> fp16 rounding, which has no hardware instruction.
+__device__ inline float to_f32(double x) {
+  float f = (float)x;
+  asm volatile("" : "+v"(f));
+  return f;
+}
+
 __device__ inline uint32_t pack_h2(_Float16 a, _Float16 b) {
   return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
@@ -89,8 +97,11 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
       const int col = c0l + e;
       double x = 0.0;
       if (r < rows_i && col < rows_j) x = ((((double)v[e] - ca) - ccol[col]) + c0) * half * scale;
-      hi[e] = (_Float16)x;
-      lo[e] = (_Float16)((x - (double)hi[e]) * 2048.0);
+      // FP64 -> FP32 -> fp16 (both hardware conversions; a direct FP64 -> fp16 rounding is
+      // a long software sequence): hi may then round one way twice, which the low plane
+      // absorbs, since it keeps the exact FP64 remainder x - hi to 11 more bits
+      hi[e] = (_Float16)to_f32(x);
+      lo[e] = (_Float16)to_f32((x - (double)(float)hi[e]) * 2048.0);
     }
     uint4 w;
     w.x = pack_h2(hi[0], hi[1]); w.y = pack_h2(hi[2], hi[3]);
