@@ -131,14 +131,22 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
       for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int q = 0; q < TILE_WORDS; ++q) zw[nb][q] = zl[q * 2 * NP + lcol + nb * 32];
+      // A fragments of step ks + 1 are read from LDS while step ks is multiplied
+      f16x8 a[4][S], an[4][S];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          a[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8) * 64 + lane]);
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
-        f16x8 a[4][S];
+        if (ks + 1 < 8) {
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
+          for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-          for (int s = 0; s < S; ++s)
-            a[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8 + ks) * 64 + lane]);
+            for (int s = 0; s < S; ++s)
+              an[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8 + ks + 1) * 64 + lane]);
+        }
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
           const uint4 bu = expand_byte((zw[nb][ks >> 1] >> ((ks & 1) * 16 + h * 8)) & 0xFFu);
@@ -152,6 +160,10 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
                   __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][S - 1], b2, acc[mb][nb], 0, 0, 0);
           }
         }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int s = 0; s < S; ++s) a[mb][s] = an[mb][s];
       }
     }
   }
