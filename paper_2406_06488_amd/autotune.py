@@ -12,7 +12,7 @@ from . import _lib, api
 from ._lib import check
 
 PRECS = {"f64": 0, "f32": 1, "bf16r": 2}
-MFMA_CANDIDATES = [(kc, cc) for kc in (2, 4, 8, 16) for cc in (1, 2)]
+MFMA_CANDIDATES = [(kc, cc) for kc in (2, 4, 8, 16, 32) for cc in (1, 2)]
 F64_CANDIDATES = [(kc, cc) for kc in (2, 4, 8) for cc in (1, 4, 8)]
 
 

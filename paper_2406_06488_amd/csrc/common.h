@@ -140,18 +140,28 @@ __device__ inline int tile_rows(const TestDesc& d, int i) {
 }
 
 // Row-range unit u -> (row tile i, first column tile j0, end j1).
-__device__ inline void rowk_coords(const TestDesc& d, int u, int* pi, int* pj0, int* pj1) {
+// Row unit u of a test -> (row tile i, column tiles [j0, j1)).  Row i holds the stored
+// tiles j = i .. nt-1 cut into ceil((nt - i) / kc) units of kc tiles (the last one shorter);
+// units are numbered row by row.  The walk over rows uses no division inside the loop: with
+// q = nt - i, the unit count ceil(q / kc) drops by one exactly when (q - 1) % kc was 0.
+__host__ __device__ inline void rowk_coords(const TestDesc& d, int u, int* pi, int* pj0,
+                                            int* pj1) {
+  const int kc = d.kc;
   int i = 0, start = 0;
-  while (true) {
-    int len = (d.nt - i + d.kc - 1) / d.kc;
-    if (u < start + len) break;
+  int len = (d.nt + kc - 1) / kc, r = (d.nt - 1) % kc;
+  while (u >= start + len) {
     start += len;
     ++i;
+    if (r == 0) {
+      --len;
+      r = kc - 1;
+    } else {
+      --r;
+    }
   }
-  int c = u - start;
   *pi = i;
-  *pj0 = i + c * d.kc;
-  int e = *pj0 + d.kc;
+  *pj0 = i + (u - start) * kc;
+  const int e = *pj0 + kc;
   *pj1 = e < d.nt ? e : d.nt;
 }
 

@@ -109,6 +109,15 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
     }
   };
 
+  // row weights for the final fold, fetched now so their latency hides behind the tiles
+  uint32_t wzf[2][4];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+      wzf[nb][mb] = active ? Z[(int64_t)(u.i * TILE_WORDS + mb) * BP + (int64_t)u.cb * NP + lcol +
+                               nb * 32]
+                           : 0u;
   f32x16 acc[4][2];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -140,6 +149,10 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
           a[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8) * 64 + lane]);
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
+        // this step's fragments (read one step earlier) have landed; waiting here, before
+        // the next reads are issued, keeps at most 8 LDS reads in flight
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
+        __builtin_amdgcn_sched_barrier(0);
         if (ks + 1 < 8) {
 #pragma unroll
           for (int mb = 0; mb < 4; ++mb)
@@ -147,6 +160,9 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
             for (int s = 0; s < S; ++s)
               an[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8 + ks + 1) * 64 + lane]);
         }
+        // keep those reads ahead of this step's products (the scheduler would otherwise
+        // sink them and wait on them before the first product)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
           const uint4 bu = expand_byte((zw[nb][ks >> 1] >> ((ks & 1) * 16 + h * 8)) & 0xFFu);
@@ -160,6 +176,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
                   __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][S - 1], b2, acc[mb][nb], 0, 0, 0);
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
@@ -175,7 +192,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
     double q = 0.0;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      const uint32_t wz = Z[(int64_t)(u.i * TILE_WORDS + mb) * BP + col];
+      const uint32_t wz = wzf[nb][mb];
       float f = 0.0f;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {

@@ -72,17 +72,32 @@ static uint64_t tune_generation() {
 }
 
 // Resampling work shape for a test: (column tiles per workgroup, chunks per workgroup).
+// Without a tuned rule: 16 column tiles per workgroup (each workgroup's start-up -- its
+// first tile load and the fold at the end -- is paid once per unit), halved while the
+// launch would have fewer than 512 workgroups (two per CU), so small tests still spread
+// over the chip.
 static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
-  *kc = 8;
   *cc = r.prec == ETEST_PREC_F64 ? MAX_CC : 2;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  const int64_t n = r.nx + r.ny;
-  for (const TuneRule& t : g_tune)
-    if (t.prec == r.prec && n >= t.n_lo && n < t.n_hi) {
-      *kc = t.kc;
-      *cc = t.cc;
-      return;
-    }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int64_t n = r.nx + r.ny;
+    for (const TuneRule& t : g_tune)
+      if (t.prec == r.prec && n >= t.n_lo && n < t.n_hi) {
+        *kc = t.kc;
+        *cc = t.cc;
+        return;
+      }
+  }
+  const int64_t nt = (r.nx + TILE - 1) / TILE + (r.ny + TILE - 1) / TILE;
+  const int64_t chunks = (r.B + 1 + NP - 1) / NP;
+  const int64_t ncr = (chunks + *cc - 1) / *cc;
+  *kc = 16;
+  while (*kc > 2) {
+    int64_t nrk = 0;
+    for (int64_t i = 0; i < nt; ++i) nrk += (nt - i + *kc - 1) / *kc;
+    if (nrk * ncr >= 512) break;
+    *kc /= 2;
+  }
 }
 
 TestPlan make_plan(const etest_request& r, int64_t kc_override) {

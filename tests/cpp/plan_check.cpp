@@ -86,7 +86,31 @@ static void check_plan(const etest_request& r, bool internal) {
         "part outside");
 }
 
+// Row units of the resampling stage: rowk_coords against a plain enumeration (row by row,
+// kc tiles at a time); together the units cover every stored tile (i <= j) exactly once.
+static void check_row_units() {
+  for (int nt = 1; nt <= 80; ++nt)
+    for (int kc = 1; kc <= 40; ++kc) {
+      TestDesc d{};
+      d.nt = nt;
+      d.kc = kc;
+      int u = 0;
+      for (int i = 0; i < nt; ++i)
+        for (int j0 = i; j0 < nt; j0 += kc, ++u) {
+          int gi, g0, g1;
+          rowk_coords(d, u, &gi, &g0, &g1);
+          const int e = j0 + kc < nt ? j0 + kc : nt;
+          CHECK(gi == i && g0 == j0 && g1 == e, "nt %d kc %d unit %d: (%d,%d,%d) vs (%d,%d,%d)",
+                nt, kc, u, gi, g0, g1, i, j0, e);
+        }
+      int nrk = 0;
+      for (int i = 0; i < nt; ++i) nrk += (nt - i + kc - 1) / kc;
+      CHECK(u == nrk, "nt %d kc %d: %d units enumerated, %d counted", nt, kc, u, nrk);
+    }
+}
+
 int main() {
+  check_row_units();
   const int precs[3] = {ETEST_PREC_F64, ETEST_PREC_F32, ETEST_PREC_BF16_REFINED};
   const int64_t shapes[][4] = {{1, 1, 1, 0},       {1, 5, 3, 40},       {100, 100, 10, 1000},
                                {129, 127, 64, 255}, {2000, 2000, 1000, 10000},
