@@ -139,7 +139,6 @@ __device__ inline int tile_rows(const TestDesc& d, int i) {
   return r < TILE ? r : TILE;
 }
 
-// Row-range unit u -> (row tile i, first column tile j0, end j1).
 // Row unit u of a test -> (row tile i, column tiles [j0, j1)).  Row i holds the stored
 // tiles j = i .. nt-1 cut into ceil((nt - i) / kc) units of kc tiles (the last one shorter);
 // units are numbered row by row.  The walk over rows uses no division inside the loop: with

@@ -17,7 +17,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int LDS_ROW_F32 = 36;   // 32 staged k + 4 pad (floats)
 constexpr int LDS_ROW_BF16 = 72;  // 64 staged k + 8 pad (bf16)
-constexpr int TILE_LDS = TILE + 1;
 
 struct TileCtx {
   int t, i, j;
@@ -69,126 +68,116 @@ __device__ inline BlockOut partner_out(const TestDesc& d, int t) {
                   d.ptsum + (int64_t)t * TSUM_STRIDE, d.ptmax + (int64_t)t * TMAX_PER_TILE};
 }
 
-// Epilogue through LDS, half a tile (64 rows) at a time so the workgroup needs at most
-// ~36 KB of LDS: the waves holding those rows write their values, then FP64 row sums
-// (complete per half), column sums (accumulated over both halves in row order) and a
-// coalesced store of the half tile.  v[mb][nb][e] holds the block value of row
-// wm*64 + mb*32 + 8*(e/4) + 4*h + e%4, column wn*64 + nb*32 + lane%32.
 constexpr int HALF = TILE / 2;
-// Entries (v) of a full tile -> block values of one output through LDS, half a tile at a
-// time: FP64 row sums (complete per half), column sums per half, coalesced store
-// and the tile max.  v[mb][nb][e] is the entry of row wm*64 + mb*32 + 8*(e/4) + 4*h + e%4,
-// column wn*64 + nb*32 + lr.
-template <bool TRANSFORM>
-__device__ inline void finish_tile_f32(const TileCtx& c, float* tl, const f32x16 (&v)[2][2],
-                                       int wm, int wn, int h, int lr, const BlockOut o) {
-  __shared__ unsigned int tile_max_bits;
+
+// Epilogue through LDS, half a tile (64 rows) at a time, so a workgroup needs ~34 KB of LDS
+// for it.  Row stride 132 floats: rows stay 16-byte aligned for vector reads, and the bank
+// of (row, col) is (4 row + col) % 32, which the patterns below keep distinct within every
+// 32 lanes.
+constexpr int TILE_LDS = TILE + 4;
+
+// Staged half tile (64 rows of block values) -> FP64 row sums, FP64 column sums of the
+// half, the stored rows and the running max |value|.  All 256 threads take part:
+//  row sums: four threads per row, thread q reading columns q*32 + (k + q) % 32;
+//  column sums: two threads per column in one wave (rows 0..31 and 32..63);
+//  store: float4 reads of whole rows (32 lanes per row), coalesced float4 stores.
+__device__ inline void emit_half(const BlockOut& o, int half, const float* tl, float& vmax) {
   const int tid = threadIdx.x;
-  float vmax = 0.0f;
-  __syncthreads();
-  if (tid == 0) tile_max_bits = 0u;
-  for (int half = 0; half < 2; ++half) {
-    __syncthreads();
-    if (wm == half) {
-      for (int mb = 0; mb < 2; ++mb)
-        for (int nb = 0; nb < 2; ++nb)
-          for (int e = 0; e < 16; ++e) {
-            const int r = mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);  // row within the half
-            const int col = wn * 64 + nb * 32 + lr;
-            // TRANSFORM: v holds squared distances; otherwise the block values already
-            tl[r * TILE_LDS + col] =
-                TRANSFORM ? block_value_f32(o.kind, o.gamma, c, half * HALF + r, col, v[mb][nb][e])
-                          : v[mb][nb][e];
-          }
+  {
+    const int row = tid >> 2, q = tid & 3;
+    const float* src = tl + row * TILE_LDS + q * 32;
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) {
+      const float x = src[(k + q) & 31];
+      s += (double)x;
+      vmax = fmaxf(vmax, fabsf(x));
     }
-    __syncthreads();
-    if (tid < HALF) {
-      double s = 0.0;
-      for (int k = 0; k < TILE; ++k) {
-        const float x = tl[tid * TILE_LDS + k];
-        s += (double)x;
-        vmax = fmaxf(vmax, fabsf(x));
-      }
-      o.tsum[half * HALF + tid] = s;
-    } else if (tid >= TILE) {
-      const int col = tid - TILE;
-      double colsum = 0.0;
-      for (int k = 0; k < HALF; ++k) colsum += (double)tl[k * TILE_LDS + col];
-      o.tsum[TILE * (1 + half) + col] = colsum;
-    }
-    for (int e = tid; e < HALF * TILE; e += 256)
-      o.D[half * HALF * TILE + e] = tl[(e / TILE) * TILE_LDS + (e % TILE)];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (q == 0) o.tsum[half * HALF + row] = s;
   }
-  // non-negative floats order like their bit patterns
-  if (tid < HALF) atomicMax(&tile_max_bits, __float_as_uint(vmax));
-  __syncthreads();
-  if (tid == 0) {
-    o.tmax[0] = __uint_as_float(tile_max_bits);
-    o.tmax[1] = 0.0f;
+  {
+    const int col = (tid >> 6) * 32 + (tid & 31), part = (tid >> 5) & 1;
+    const float* src = tl + part * 32 * TILE_LDS + col;
+    double s = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) s += (double)src[k * TILE_LDS];
+    s += __shfl_xor(s, 32, 64);
+    if (part == 0) o.tsum[TILE * (1 + half) + col] = s;
+  }
+  float4* dst = (float4*)(o.D + half * HALF * TILE);
+#pragma unroll
+  for (int k = 0; k < HALF * TILE / 4 / 256; ++k) {
+    const int f = tid + 256 * k;
+    dst[f] = *(const float4*)(tl + (f >> 5) * TILE_LDS + 4 * (f & 31));
   }
 }
 
-// Squared distances (v) of a full tile -> block values of the test's own output and, with
-// has1, of the MMD test it feeds.  The squared distances are staged in LDS once per half
-// tile and each output is derived from them as it is read, so v is not held across two
-// passes.
-__device__ inline void finish_tile_dual(const TileCtx& c, float* tl, const f32x16 (&v)[2][2],
-                                        int wm, int wn, int h, int lr, const BlockOut o0,
-                                        const BlockOut o1, const bool has1) {
+// Full tile in registers -> one output (DUAL false: v holds its block values) or the
+// test's own output and, with has1, the MMD test it feeds (DUAL true: v holds squared
+// distances; each output's values are formed from the staged copy in place, once per
+// entry, so no second set of values is held in registers).  v[mb][nb][e] is the entry of
+// row wm*64 + mb*32 + 8*(e/4) + 4*h + e%4, column wn*64 + nb*32 + lr: the waves with
+// wm == half hold half `half`.
+template <bool DUAL>
+__device__ inline void finish_tile(const TileCtx& c, float* tl, const f32x16 (&v)[2][2], int wm,
+                                   int wn, int h, int lr, const BlockOut o0, const BlockOut o1,
+                                   const bool has1) {
   __shared__ unsigned int tile_max_bits[2];
   const int tid = threadIdx.x;
   float vmax0 = 0.0f, vmax1 = 0.0f;
-  // row sums, column sums and store of one output from the squared distances in tl
-  auto emit = [&](const BlockOut o, int half, float& vmax) {
-    if (tid < HALF) {
-      const int r = half * HALF + tid;
-      double s = 0.0;
-      for (int k = 0; k < TILE; ++k) {
-        const float x = block_value_f32(o.kind, o.gamma, c, r, k, tl[tid * TILE_LDS + k]);
-        s += (double)x;
-        vmax = fmaxf(vmax, fabsf(x));
-      }
-      o.tsum[r] = s;
-    } else if (tid >= TILE) {
-      const int col = tid - TILE;
-      double colsum = 0.0;
-      for (int k = 0; k < HALF; ++k)
-        colsum += (double)block_value_f32(o.kind, o.gamma, c, half * HALF + k, col,
-                                          tl[k * TILE_LDS + col]);
-      o.tsum[TILE * (1 + half) + col] = colsum;
-    }
-    for (int e = tid; e < HALF * TILE; e += 256) {
-      const int rl = e / TILE, col = e % TILE;
-      o.D[half * HALF * TILE + e] =
-          block_value_f32(o.kind, o.gamma, c, half * HALF + rl, col, tl[rl * TILE_LDS + col]);
-    }
-  };
-  __syncthreads();
-  if (tid < 2) tile_max_bits[tid] = 0u;
-  for (int half = 0; half < 2; ++half) {
+  auto stage = [&](int half) {
     __syncthreads();
     if (wm == half) {
+#pragma unroll
       for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
         for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
           for (int e = 0; e < 16; ++e) {
             const int r = mb * 32 + 8 * (e >> 2) + 4 * h + (e & 3);  // row within the half
             tl[r * TILE_LDS + wn * 64 + nb * 32 + lr] = v[mb][nb][e];
           }
     }
     __syncthreads();
-    emit(o0, half, vmax0);
-    if (has1) emit(o1, half, vmax1);
+  };
+  auto transform = [&](int half, int kind, double gamma) {
+#pragma unroll 2
+    for (int k = 0; k < HALF * TILE / 256; ++k) {
+      const int f = tid + 256 * k, r = f >> 7, col = f & (TILE - 1);
+      float* q = tl + r * TILE_LDS + col;
+      *q = block_value_f32(kind, gamma, c, half * HALF + r, col, *q);
+    }
+    __syncthreads();
+  };
+  if (tid < 2) tile_max_bits[tid] = 0u;
+#pragma nounroll
+  for (int half = 0; half < 2; ++half) {
+    stage(half);
+    if (DUAL) transform(half, o0.kind, o0.gamma);
+    emit_half(o0, half, tl, vmax0);
+    if (DUAL && has1) {
+      stage(half);
+      transform(half, o1.kind, o1.gamma);
+      emit_half(o1, half, tl, vmax1);
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    vmax0 = fmaxf(vmax0, __shfl_xor(vmax0, m, 64));
+    if (DUAL) vmax1 = fmaxf(vmax1, __shfl_xor(vmax1, m, 64));
   }
   // non-negative floats order like their bit patterns
-  if (tid < HALF) {
+  if ((tid & 63) == 0) {
     atomicMax(&tile_max_bits[0], __float_as_uint(vmax0));
-    if (has1) atomicMax(&tile_max_bits[1], __float_as_uint(vmax1));
+    if (DUAL && has1) atomicMax(&tile_max_bits[1], __float_as_uint(vmax1));
   }
   __syncthreads();
   if (tid == 0) {
     o0.tmax[0] = __uint_as_float(tile_max_bits[0]);
     o0.tmax[1] = 0.0f;
-    if (has1) {
+    if (DUAL && has1) {
       o1.tmax[0] = __uint_as_float(tile_max_bits[1]);
       o1.tmax[1] = 0.0f;
     }
@@ -258,7 +247,7 @@ template <bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_gram_f32(const TestDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ offs, int ntests) {
-  __shared__ float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F32 ? HALF * TILE_LDS
+  __shared__ __attribute__((aligned(16))) float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F32 ? HALF * TILE_LDS
                                                                   : 2 * TILE * LDS_ROW_F32];
   const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
   const int ti = find_test(offs, ntests, bid);
@@ -332,11 +321,12 @@ k_gram_f32(const TestDesc* __restrict__ descs,
   // outputs; plain launches turn them into block values at once
   if (DUAL) {
     gram_epilogue<false>(d, c, acc, wm, wn, h, lr);
-    finish_tile_dual(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
-                     d.pD != nullptr);
+    finish_tile<true>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
+                      d.pD != nullptr);
   } else {
     gram_epilogue<true>(d, c, acc, wm, wn, h, lr);
-    finish_tile_f32<false>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t));
+    const BlockOut o = own_out(d, c.t);
+    finish_tile<false>(c, smem, acc, wm, wn, h, lr, o, o, false);
   }
 }
 
@@ -347,7 +337,7 @@ template <bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_gram_bf16(const TestDesc* __restrict__ descs,
                                                    const int64_t* __restrict__ offs, int ntests) {
-  __shared__ float smem[HALF * TILE_LDS > TILE * LDS_ROW_BF16 ? HALF * TILE_LDS
+  __shared__ __attribute__((aligned(16))) float smem[HALF * TILE_LDS > TILE * LDS_ROW_BF16 ? HALF * TILE_LDS
                                                               : TILE * LDS_ROW_BF16];
   const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
   const int ti = find_test(offs, ntests, bid);
@@ -417,11 +407,12 @@ k_gram_bf16(const TestDesc* __restrict__ descs,
   // outputs; plain launches turn them into block values at once
   if (DUAL) {
     gram_epilogue<false>(d, c, acc, wm, wn, h, lr);
-    finish_tile_dual(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
-                     d.pD != nullptr);
+    finish_tile<true>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
+                      d.pD != nullptr);
   } else {
     gram_epilogue<true>(d, c, acc, wm, wn, h, lr);
-    finish_tile_f32<false>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t));
+    const BlockOut o = own_out(d, c.t);
+    finish_tile<false>(c, smem, acc, wm, wn, h, lr, o, o, false);
   }
 }
 

@@ -117,8 +117,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   // fp16 planes of the centred blocks: hi + lo 2^-11 keeps ~22 significant bits of each
   // centred entry.  One plane (11 bits) is not enough even for the BF16 form: a statistic
   // is a sum with heavy cancellation, and on small tests 11-bit entries move it by ~1e-3.
-  d.splits = r.prec == ETEST_PREC_F32 ? 2
-             : r.prec == ETEST_PREC_BF16_REFINED ? env_int("ETEST_BF16_SPLITS", 2, 1, 2) : 1;
+  d.splits = r.prec == ETEST_PREC_F64 ? 1 : 2;
   d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
   int32_t kc_t, cc_t;
   tuned_shape(r, &kc_t, &cc_t);
