@@ -25,12 +25,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // 8 membership bits -> 8 fp16 values 0.0 / 1.0 (element k = bit k).  m = byte * 0x8001
-// holds bit k at positions k and k + 15, so (m >> 2q) & 0x10001 puts bits 2q and 2q+1
-// at positions 0 and 16; times 0x3C00 (fp16 1.0) that is the packed pair.
+// holds bit k at positions k and k + 15, so dword q's two bits 2q and 2q+1 sit at positions
+// 2q and 2q + 16; masking them in place and multiplying by 0x3C00 >> 2q (an integer, as
+// 0x3C00 = 15 * 2^10) puts fp16 1.0 at bits 0 and 16.
 __device__ inline uint4 expand_byte(uint32_t byte) {
   const uint32_t m = byte * 0x8001u;
-  return make_uint4((m & 0x10001u) * 0x3C00u, ((m >> 2) & 0x10001u) * 0x3C00u,
-                    ((m >> 4) & 0x10001u) * 0x3C00u, ((m >> 6) & 0x10001u) * 0x3C00u);
+  return make_uint4((m & 0x10001u) * 0x3C00u, (m & 0x40004u) * 0x0F00u,
+                    (m & 0x100010u) * 0x03C0u, (m & 0x400040u) * 0x00F0u);
 }
 // The same bits worth 2^-11 (fp16 0x1000) for the low plane: 0x3C00 & 0x1000 = 0x1000.
 __device__ inline uint4 low_weights(uint4 u) {

@@ -400,6 +400,11 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   end(6, st);
 }
 
+// Fork/join and stage events only order work on this device (and time it): they skip the
+// system-scope fence a default event adds on every record, which costs several
+// microseconds per record between the kernels of a pass.
+constexpr unsigned kFenceFree = hipEventDisableSystemFence;
+
 // Per-thread auxiliary stream and fork/join events.
 static const Fork* thread_fork() {
   static thread_local Fork f;
@@ -407,18 +412,21 @@ static const Fork* thread_fork() {
   if (state == 0) {
     state = -1;
     if (hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking) == hipSuccess &&
-        hipEventCreateWithFlags(&f.start, hipEventDisableTiming) == hipSuccess &&
-        hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess)
+        hipEventCreateWithFlags(&f.start, kFenceFree | hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&f.done, kFenceFree | hipEventDisableTiming) == hipSuccess)
       state = 1;
   }
   return state == 1 ? &f : nullptr;
 }
 
 // ------------------------------------------------------------------ stage timing
+// Each enqueued pass takes its own set of stage events, so passes enqueued back to back
+// without a wait in between (the asynchronous entry points) are all timed; the sets are
+// read, and returned to the spare list, when the host collects.
 struct Profile {
   bool on = false;
-  bool ready = false;
-  StageEvents ev;
+  uint32_t mask = 0;
+  std::vector<StageEvents*> pending, spare;
   double ms[NSTAGE] = {};
   int64_t launches[NSTAGE] = {};
 };
@@ -426,27 +434,39 @@ static thread_local Profile g_prof;
 
 static const StageEvents* profile_events() {
   if (!g_prof.on) return nullptr;
-  if (!g_prof.ready) {
+  StageEvents* ev = nullptr;
+  if (!g_prof.spare.empty()) {
+    ev = g_prof.spare.back();
+    g_prof.spare.pop_back();
+  } else {
+    ev = new StageEvents;
     for (int k = 0; k < NSTAGE; ++k)
-      if (hipEventCreate(&g_prof.ev.begin[k]) != hipSuccess ||
-          hipEventCreate(&g_prof.ev.end[k]) != hipSuccess)
+      if (hipEventCreateWithFlags(&ev->begin[k], kFenceFree) != hipSuccess ||
+          hipEventCreateWithFlags(&ev->end[k], kFenceFree) != hipSuccess) {
+        delete ev;  // (events created so far are leaked; creation failing means a dead device)
         return nullptr;
-    g_prof.ready = true;
+      }
   }
-  return &g_prof.ev;
+  ev->mask = g_prof.mask;
+  g_prof.pending.push_back(ev);
+  return ev;
 }
 
-// After the stream has synchronised.
+// Adds the elapsed times of every pending pass (waiting for their last events).
 static void profile_collect() {
-  if (!g_prof.on || !g_prof.ready) return;
-  for (int k = 0; k < NSTAGE; ++k) {
-    float ms = 0.0f;
-    if (!(g_prof.ev.mask >> k & 1u)) continue;
-    if (hipEventElapsedTime(&ms, g_prof.ev.begin[k], g_prof.ev.end[k]) == hipSuccess) {
-      g_prof.ms[k] += ms;
-      g_prof.launches[k] += 1;
+  for (StageEvents* ev : g_prof.pending) {
+    for (int k = 0; k < NSTAGE; ++k) {
+      if (!(ev->mask >> k & 1u)) continue;
+      float ms = 0.0f;
+      if (hipEventSynchronize(ev->end[k]) == hipSuccess &&
+          hipEventElapsedTime(&ms, ev->begin[k], ev->end[k]) == hipSuccess) {
+        g_prof.ms[k] += ms;
+        g_prof.launches[k] += 1;
+      }
     }
+    g_prof.spare.push_back(ev);
   }
+  g_prof.pending.clear();
 }
 
 etest_status dev_to_result(const DevResult& r, etest_result* out) {
@@ -739,9 +759,10 @@ etest_status etest_tune_clear(void) {
 
 etest_status etest_profile_enable(int32_t on) {
   if (on < 0) return set_error(ETEST_EINVAL, "profile mask must be >= 0");
+  profile_collect();  // passes still pending belong to the previous setting: drop their times
   g_prof.on = on != 0;
   // 1: every stage; any other value: a bit mask of stages shifted left by one
-  g_prof.ev.mask = on == 1 ? (1u << NSTAGE) - 1u : ((uint32_t)on >> 1) & ((1u << NSTAGE) - 1u);
+  g_prof.mask = on == 1 ? (1u << NSTAGE) - 1u : ((uint32_t)on >> 1) & ((1u << NSTAGE) - 1u);
   for (int k = 0; k < NSTAGE; ++k) {
     g_prof.ms[k] = 0.0;
     g_prof.launches[k] = 0;
@@ -751,6 +772,7 @@ etest_status etest_profile_enable(int32_t on) {
 
 etest_status etest_profile_read(double* ms, int64_t* launches, int32_t n) {
   if (!ms || !launches || n < 0 || n > NSTAGE) return set_error(ETEST_EINVAL, "bad arguments");
+  profile_collect();
   for (int k = 0; k < n; ++k) {
     ms[k] = g_prof.ms[k];
     launches[k] = g_prof.launches[k];
@@ -817,7 +839,7 @@ static etest_status enqueue_async(const etest_request* req, int kind, etest_resu
   if (s != ETEST_OK) return s;
   s = place_batch(&b, st, true);
   if (s != ETEST_OK) return s;
-  enqueue_batch(b, st);
+  enqueue_batch(b, st, nullptr, profile_events(), thread_fork());
   // etest_result is the leading part of DevResult
   hipError_t e = hipMemcpyAsync(d_out, b.d_results, sizeof(etest_result), hipMemcpyDeviceToDevice, st);
   free_batch(&b, st, true);
