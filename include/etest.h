@@ -210,8 +210,10 @@ etest_status etest_footprint(const etest_request* req, int64_t* bytes);
 /* Check a request's arguments without touching the device (same rules as every call). */
 etest_status etest_validate(const etest_request* req);
 
-/* Stage timing of the calling thread's etest_run / etest_batch / ed_test / mmd_test calls: when on, HIP
-   events on the call's stream bracket each stage and their elapsed times accumulate.
+/* Stage timing of the calling thread's etest_run / etest_batch / ed_test / mmd_test and
+   ed_test_async / mmd_test_async calls: when on, HIP events on the call's stream bracket
+   each stage (every pass has its own event set, so passes enqueued back to back are all
+   timed) and their elapsed times accumulate when the host collects them.
    Stages: 0 staging (column means, cast, norms), 1 blocks (Gram + epilogue), 2 split stream,
    3 block sums + observed statistic, 4 centring, 5 resampling, 6 statistics + p-value.
    on = 0: off; 1: every stage; otherwise bits 1..7 of `on` select stages 0..6 (bit k+1 =
@@ -219,7 +221,9 @@ etest_status etest_validate(const etest_request* req);
    a marker between launches).  Enabling also resets the totals. */
 etest_status etest_profile_enable(int32_t on);
 
-/* Accumulated milliseconds and launch counts per stage (arrays of n <= 7 entries). */
+/* Accumulated milliseconds and launch counts per stage (arrays of n <= 7 entries).  Passes
+   enqueued asynchronously and not yet collected are waited for and added first.  Changing
+   the setting with etest_profile_enable drops the times of passes still pending. */
 etest_status etest_profile_read(double* ms, int64_t* launches, int32_t n);
 
 /* ---- Tuning of the resampling stage's work shape ---- */

@@ -46,8 +46,18 @@ struct DevResult {
   int32_t status, pad;
 };
 
+// Plane formats of the centred tiles that the resampling stage multiplies (FP32 and
+// BF16-refined forms; the FP64 form keeps FP64 tiles):
+//  PLANES_F16_F16:  hi = fp16(v), lo = fp16((v - hi) 2^11); v to ~2^-22 of itself.
+//  PLANES_F16_E4M3: hi = fp16(v), lo = e4m3((v - hi) 2^5) (fp8, OCP); v to ~2^-15.
+constexpr int PLANES_F16_F16 = 2;
+constexpr int PLANES_F16_E4M3 = 3;
+__host__ __device__ inline int plane_bytes_per_entry(int pfmt) {
+  return pfmt == PLANES_F16_E4M3 ? 3 : 4;
+}
+
 struct TestDesc {
-  int32_t kind, prec, splits, refine;
+  int32_t kind, prec, pfmt, refine;  // pfmt: plane format of the centred tiles (PLANES_*)
   int32_t nx, ny, p, p_pad;
   int32_t tx, ty, nt, ntiles;
   int32_t kc, n_rowk, nrowchunks, cc;  // cc: split-column chunks per resampling workgroup
@@ -162,6 +172,26 @@ __host__ __device__ inline void rowk_coords(const TestDesc& d, int u, int* pi, i
   *pj0 = i + (u - start) * kc;
   const int e = *pj0 + kc;
   *pj1 = e < d.nt ? e : d.nt;
+}
+
+// FP32 -> fp8 E4M3 in the OCP layout the gfx950 fp8 MFMA reads (bias 7, no infinities,
+// 0x7F / 0xFF are NaN, largest finite 448): round to nearest even, saturating at +-448;
+// subnormals (multiples of 2^-9) kept.  Finite inputs only; zero of either sign -> 0.
+__host__ __device__ inline uint32_t f32_to_e4m3(float x) {
+  const uint32_t sign = (__builtin_bit_cast(uint32_t, x) >> 24) & 0x80u;
+  const float a = __builtin_fabsf(x);
+  uint32_t code;
+  if (a < 0.015625f) {
+    // below 2^-6: multiples of 2^-9; code 8 (2^-6, the smallest normal) follows on
+    code = (uint32_t)__builtin_rintf(a * 512.0f);
+  } else {
+    uint32_t ua = __builtin_bit_cast(uint32_t, a);
+    ua += 0x7FFFFu + ((ua >> 20) & 1u);  // 23-bit mantissa -> 3 bits, nearest even
+    const uint32_t e = (ua >> 23) - 120u;  // exponent rebiased from 127 to 7
+    code = e > 15u ? 0x7Eu : ((e << 3) | ((ua >> 20) & 7u));
+    if (code > 0x7Eu) code = 0x7Eu;
+  }
+  return code ? (sign | code) : 0u;
 }
 
 // Round-to-nearest-even float -> bf16 bits (finite inputs).

@@ -10,12 +10,18 @@
 // a single quadratic form over the three stored blocks.  Diagonal tiles are
 // halved, so that z^T Dc z = 2 * sum over stored tiles (i <= j) of z_i^T T_ij z_j.
 //
-// FP32/BF16 forms: the centred value, scaled by the test's power of two 2^e (so every
-// value fits fp16), becomes two fp16 planes hi = fp16(v) and lo = fp16((v - hi) 2^11);
-// the resampling stage multiplies lo by split bits worth 2^-11, so hi + lo 2^-11 holds
-// v to about 2^-22 of itself with both products exact.  Planes are laid out in
-// v_mfma_f32_32x32x16_f16 A-fragment order: fragment (mb, ks) of a tile is 64 lanes x
-// 8 values, lane = row%32 + 32 * ((col%16)/8), for rows 32 mb.. and columns 16 ks.. .
+// FP32/BF16 forms: the centred value v, scaled by the test's power of two 2^e (so that
+// |v| <= 2^14), becomes two planes whose products with split bits are exact:
+//  FP32 form: hi = fp16(v), lo = fp16((v - hi) 2^11), multiplied by bits worth 1 and
+//    2^-11: hi + lo 2^-11 holds v to about 2^-22 of itself;
+//  BF16-refined form: hi = fp16(v), lo = e4m3((v - hi) 2^5) (|lo| <= 2^8 < 448), multiplied
+//    by bits worth 1 and 2^-5 on the fp8 MFMA: v to about 2^-15 of itself, 3 bytes per entry.
+// The hi (and fp16 lo) plane is laid out in v_mfma_f32_32x32x16_f16 A-fragment order:
+// fragment (mb, ks) of a tile is 64 lanes x 8 values, lane = row%32 + 32 * ((col%16)/8),
+// for rows 32 mb.. and columns 16 ks.. .  The e4m3 plane follows the 32x32x64 fp8
+// A-fragment order: fragment (mb, kb) holds rows 32 mb.. and columns 64 kb.., lane
+// row%32 + 32 * ((col%64)/32) holding 32 bytes (columns in order), stored as two 16-byte
+// halves: [fragment][half][lane][16 bytes].
 // FP64 form: one FP64 row-major tile.
 #include "common.h"
 
@@ -60,7 +66,7 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
   const double c0 = d.obs[4] / (n * n);
   const double scale = d.obs[5];
   const double half = i == j ? 0.5 : 1.0;
-  const int S = d.splits;
+  const bool f8lo = d.pfmt == PLANES_F16_E4M3;
   {
     const int r = threadIdx.x & (TILE - 1);
     const int blk = threadIdx.x < TILE ? i : j;
@@ -71,7 +77,9 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
   }
   __syncthreads();
   const float* Dt = (const float*)d.D + (int64_t)t * TILE * TILE;
-  uint16_t* P = (uint16_t*)d.planes + (int64_t)t * S * TILE * TILE;
+  uint8_t* P = (uint8_t*)d.planes + (int64_t)t * plane_bytes_per_entry(d.pfmt) * TILE * TILE;
+  uint16_t* Phi = (uint16_t*)P;
+  uint8_t* Plo = P + 2 * TILE * TILE;
   // every load of the thread first (16 x 16 B in flight), then the conversions
   constexpr int NQ = TILE * TILE / 8 / 256;
   float4 raw[NQ][2];
@@ -92,6 +100,7 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
                         raw[it][1].x, raw[it][1].y, raw[it][1].z, raw[it][1].w};
     const double ca = crow[r];
     _Float16 hi[8], lo[8];
+    uint32_t lo8[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int col = c0l + e;
@@ -99,18 +108,30 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
       if (r < rows_i && col < rows_j) x = ((((double)v[e] - ca) - ccol[col]) + c0) * half * scale;
       // FP64 -> FP32 -> fp16 (both hardware conversions; a direct FP64 -> fp16 rounding is
       // a long software sequence): hi may then round one way twice, which the low plane
-      // absorbs, since it keeps the exact FP64 remainder x - hi to 11 more bits
+      // absorbs, since it is formed from the exact FP64 remainder x - hi
       hi[e] = (_Float16)to_f32(x);
-      lo[e] = (_Float16)to_f32((x - (double)(float)hi[e]) * 2048.0);
+      const double rem = x - (double)(float)hi[e];
+      if (f8lo) lo8[e] = f32_to_e4m3(to_f32(rem * 32.0));
+      else lo[e] = (_Float16)to_f32(rem * 2048.0);
     }
     uint4 w;
     w.x = pack_h2(hi[0], hi[1]); w.y = pack_h2(hi[2], hi[3]);
     w.z = pack_h2(hi[4], hi[5]); w.w = pack_h2(hi[6], hi[7]);
-    *(uint4*)(P + (int64_t)q * 8) = w;
-    if (S > 1) {
+    *(uint4*)(Phi + (int64_t)q * 8) = w;
+    if (f8lo) {
+      // columns c0l .. c0l+7 are bytes (c0l % 16) .. +7 of half (c0l % 32) / 16 of lane
+      // (r % 32) + 32 ((c0l % 64) / 32) in fragment (mb, c0l / 64)
+      const int kb = c0l >> 6, g = (c0l >> 5) & 1, hf = (c0l >> 4) & 1;
+      const int64_t off = ((int64_t)((mb * 2 + kb) * 2 + hf) * 64 + (lane & 31) + 32 * g) * 16 +
+                          (c0l & 15);
+      uint2 b;
+      b.x = lo8[0] | (lo8[1] << 8) | (lo8[2] << 16) | (lo8[3] << 24);
+      b.y = lo8[4] | (lo8[5] << 8) | (lo8[6] << 16) | (lo8[7] << 24);
+      *(uint2*)(Plo + off) = b;
+    } else {
       w.x = pack_h2(lo[0], lo[1]); w.y = pack_h2(lo[2], lo[3]);
       w.z = pack_h2(lo[4], lo[5]); w.w = pack_h2(lo[6], lo[7]);
-      *(uint4*)(P + TILE * TILE + (int64_t)q * 8) = w;
+      *(uint4*)(Phi + TILE * TILE + (int64_t)q * 8) = w;
     }
   }
 }

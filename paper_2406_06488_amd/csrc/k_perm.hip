@@ -9,12 +9,16 @@
 // tiles make z^T Dc z = 2 * sum over stored tiles (i <= j) of z_i^T T_ij z_j.
 //
 // Work unit: (row tile i, column tiles [j0, j1), split-column chunks [cb, ce)),
-// chunk = NP = 256 splits.  FP32 / BF16 forms: the centred tiles are held as two fp16
-// planes (value = hi + lo 2^-11, see k_center.hip); membership bits expand to exact
-// fp16 B fragments worth 1 (for hi) and 2^-11 (for lo), so every product on
-// v_mfma_f32_32x32x16_f16 is exact and only the FP32 accumulation order differs from
-// an exact evaluation; partial sums per row range are reduced in FP64.  FP64 form:
-// the same quadratic form on the FP64 vector ALU, one thread per split.
+// chunk = NP = 256 splits.  FP32 / BF16 forms: the centred tiles are held as two planes
+// (see k_center.hip).  FP32 form: fp16 hi and lo (value = hi + lo 2^-11); membership bits
+// expand to exact fp16 B fragments worth 1 (for hi) and 2^-11 (for lo), both multiplied on
+// v_mfma_f32_32x32x16_f16.  BF16-refined form: fp16 hi as above and an e4m3 lo plane
+// (value = hi + lo 2^-5), whose bits expand to fp8 bytes worth 2^-5 for
+// v_mfma_scale_f32_32x32x64_f8f6f4 (unit block scales), which takes 64 columns per
+// instruction at about 1.6x the fp16 rate.  Every product is exact, so only the FP32
+// accumulation order differs from an exact evaluation; partial sums per row range are
+// reduced in FP64.  FP64 form: the same quadratic form on the FP64 vector ALU, one thread
+// per split.
 #include "common.h"
 
 namespace et {
@@ -23,6 +27,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // 8 membership bits -> 8 fp16 values 0.0 / 1.0 (element k = bit k).  m = byte * 0x8001
 // holds bit k at positions k and k + 15, so dword q's two bits 2q and 2q+1 sit at positions
@@ -36,6 +41,19 @@ __device__ inline uint4 expand_byte(uint32_t byte) {
 // The same bits worth 2^-11 (fp16 0x1000) for the low plane: 0x3C00 & 0x1000 = 0x1000.
 __device__ inline uint4 low_weights(uint4 u) {
   return make_uint4(u.x & 0x10001000u, u.y & 0x10001000u, u.z & 0x10001000u, u.w & 0x10001000u);
+}
+
+// 32 membership bits (bit j = column j of a 64-column step's lane group) -> 32 fp8 E4M3
+// bytes worth 2^-5 (code 0x10) or 0.  Nibble q, placed at bits 4..7, times 0x204081 puts
+// bit i of the nibble at bit 4 + 8 i (the four shifted copies do not collide there).
+__device__ inline i32x8 expand_word_e4m3(uint32_t w) {
+  i32x8 o;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t nib16 = q == 0 ? (w << 4) & 0xF0u : (w >> (4 * q - 4)) & 0xF0u;
+    o[q] = (int)((nib16 * 0x204081u) & 0x10101010u);
+  }
+  return o;
 }
 
 struct PermUnit {
@@ -77,7 +95,8 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
                                                             const int32_t* __restrict__ pcr) {
   constexpr int FR = TILE * TILE / 8;         // 16-byte fragments per plane (2048)
   constexpr int ZW = TILE_WORDS * 2 * NP / 4;  // 16-byte groups of membership words (512)
-  constexpr int BUF = S * FR + ZW;            // 16-byte slots per buffer
+  constexpr int PU = S == 3 ? FR + FR / 2 : S * FR;  // 16-byte slots of one tile's planes
+  constexpr int BUF = PU + ZW;                // 16-byte slots per buffer
   __shared__ uint4 lds[2 * BUF];
   const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
   const int ti = find_test(offs, ntests, bid);
@@ -95,9 +114,9 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
   // Queue the A tile and membership words of column tile j into buffer `buf`.
   auto issue = [&](int j, int buf) {
     uint4* dst = lds + buf * BUF;
-    const uint4* src = planes + (int64_t)tile_index(u.i, j, d.nt) * S * FR;
+    const uint4* src = planes + (int64_t)tile_index(u.i, j, d.nt) * PU;
 #pragma unroll
-    for (int r = 0; r < S * FR / PERM_THREADS; ++r) {
+    for (int r = 0; r < PU / PERM_THREADS; ++r) {
       const int q = tid + PERM_THREADS * r;
       load_to_lds16(src + q, dst + (q - lane));
     }
@@ -106,7 +125,7 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
     if (part * 4 < nch * NP) {
       const uint32_t* zsrc =
           Z + (int64_t)(j * TILE_WORDS + q) * BP + (int64_t)u.cb * NP + part * 4;
-      load_to_lds16(zsrc, dst + S * FR + (tid - lane));
+      load_to_lds16(zsrc, dst + PU + (tid - lane));
     }
   };
 
@@ -134,31 +153,46 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
     __syncthreads();                // everyone's have, and `buf ^ 1` is free again
     if (j + 1 < u.j1) issue(j + 1, buf ^ 1);
     const uint4* A = lds + buf * BUF;
-    const uint32_t* zl = (const uint32_t*)(A + S * FR);  // [q][512 columns]
+    const uint32_t* zl = (const uint32_t*)(A + PU);  // [q][512 columns]
     if (active) {
       uint32_t zw[2][TILE_WORDS];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
         for (int q = 0; q < TILE_WORDS; ++q) zw[nb][q] = zl[q * 2 * NP + lcol + nb * 32];
-      // A fragments of step ks + 1 are read from LDS while step ks is multiplied
-      f16x8 a[4][S], an[4][S];
+      // A fragments of step ks + 1 are read from LDS while step ks is multiplied.  NH fp16
+      // planes; with the e4m3 low plane (S == 3) its fragments cover 64 columns (4 steps)
+      // and are read at the first step of each 64.
+      constexpr int NH = S == 3 ? 1 : S;
+      const uint4* Alo = A + FR;  // e4m3 plane: [fragment (mb, kb)][half][lane]
+      f16x8 a[4][NH], an[4][NH];
+      i32x8 al[4];
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+        for (int s = 0; s < NH; ++s)
           a[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8) * 64 + lane]);
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
         // this step's fragments (read one step earlier) have landed; waiting here, before
-        // the next reads are issued, keeps at most 8 LDS reads in flight
+        // the next reads are issued, keeps at most 12 LDS reads in flight
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
         __builtin_amdgcn_sched_barrier(0);
+        if (S == 3 && (ks & 3) == 0) {
+          const int kb = ks >> 2;
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) {
+            const uint4 p0 = Alo[((mb * 2 + kb) * 2 + 0) * 64 + lane];
+            const uint4 p1 = Alo[((mb * 2 + kb) * 2 + 1) * 64 + lane];
+            al[mb] = i32x8{(int)p0.x, (int)p0.y, (int)p0.z, (int)p0.w,
+                           (int)p1.x, (int)p1.y, (int)p1.z, (int)p1.w};
+          }
+        }
         if (ks + 1 < 8) {
 #pragma unroll
           for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-            for (int s = 0; s < S; ++s)
+            for (int s = 0; s < NH; ++s)
               an[mb][s] = __builtin_bit_cast(f16x8, A[s * FR + (mb * 8 + ks + 1) * 64 + lane]);
         }
         // keep those reads ahead of this step's products (the scheduler would otherwise
@@ -172,16 +206,28 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
 #pragma unroll
           for (int mb = 0; mb < 4; ++mb) {
             acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][0], b1, acc[mb][nb], 0, 0, 0);
-            if (S > 1)
+            if (S == 2)
               acc[mb][nb] =
-                  __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][S - 1], b2, acc[mb][nb], 0, 0, 0);
+                  __builtin_amdgcn_mfma_f32_32x32x16_f16(a[mb][NH - 1], b2, acc[mb][nb], 0, 0, 0);
+          }
+        }
+        if (S == 3 && (ks & 3) == 0) {
+          // columns 64 kb + 32 h + j of lane group h are bit j of membership word 2 kb + h
+          const int kb = ks >> 2;
+#pragma unroll
+          for (int nb = 0; nb < 2; ++nb) {
+            const i32x8 b8 = expand_word_e4m3(h ? zw[nb][2 * kb + 1] : zw[nb][2 * kb]);
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                  al[mb], b8, acc[mb][nb], 0, 0, 0, 127, 0, 127);
           }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-          for (int s = 0; s < S; ++s) a[mb][s] = an[mb][s];
+          for (int s = 0; s < NH; ++s) a[mb][s] = an[mb][s];
       }
     }
   }
@@ -252,8 +298,9 @@ void launch_perm(int variant, int64_t blocks, hipStream_t st, const TestDesc* d,
   const dim3 g((unsigned)blocks), b(256);
   switch (variant) {
     case 0: hipLaunchKernelGGL(k_perm_f64, g, b, 0, st, d, offs, ntests, pcr); break;
-    case 1: hipLaunchKernelGGL(k_perm_mfma<1>, g, dim3(PERM_THREADS), 0, st, d, offs, ntests, pcr); break;
-    default: hipLaunchKernelGGL(k_perm_mfma<2>, g, dim3(PERM_THREADS), 0, st, d, offs, ntests, pcr); break;
+    case 2: hipLaunchKernelGGL(k_perm_mfma<2>, g, dim3(PERM_THREADS), 0, st, d, offs, ntests, pcr); break;
+    case 3: hipLaunchKernelGGL(k_perm_mfma<3>, g, dim3(PERM_THREADS), 0, st, d, offs, ntests, pcr); break;
+    default: break;
   }
 }
 

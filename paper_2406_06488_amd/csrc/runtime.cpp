@@ -117,7 +117,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   // fp16 planes of the centred blocks: hi + lo 2^-11 keeps ~22 significant bits of each
   // centred entry.  One plane (11 bits) is not enough even for the BF16 form: a statistic
   // is a sum with heavy cancellation, and on small tests 11-bit entries move it by ~1e-3.
-  d.splits = r.prec == ETEST_PREC_F64 ? 1 : 2;
+  d.pfmt = r.prec == ETEST_PREC_F64 ? 0
+           : r.prec == ETEST_PREC_F32 ? PLANES_F16_F16 : PLANES_F16_E4M3;
   d.refine = r.prec == ETEST_PREC_F64 ? 0 : 1;
   int32_t kc_t, cc_t;
   tuned_shape(r, &kc_t, &cc_t);
@@ -154,7 +155,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   sz[B_RSUM] = (size_t)npad * 2 * 8;
   sz[B_OBS] = 8 * 8;
   sz[B_PLANES] = f64 ? (size_t)d.ntiles * TILE * TILE * 8
-                     : (size_t)d.ntiles * d.splits * TILE * TILE * 2;
+                     : (size_t)d.ntiles * TILE * TILE * plane_bytes_per_entry(d.pfmt);
   sz[B_Z] = (size_t)(npad / 32) * d.B_pad * 4;
   sz[B_PART] = (size_t)d.n_rowk * d.B_pad * 8;
   sz[B_PSTAT] = (size_t)d.B_pad * 8;
@@ -183,9 +184,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   P.wg[S_CENTER_SPLIT] = f64 ? 0 : d.ntiles;
   const int64_t perm_wg = perm_units(d, (int)(d.B_pad / NP));
   P.wg[S_PERM_F64] = f64 ? perm_wg : 0;
-  P.wg[S_PERM_S1] = (!f64 && d.splits == 1) ? perm_wg : 0;
-  P.wg[S_PERM_S2] = (!f64 && d.splits == 2) ? perm_wg : 0;
-  P.wg[S_PERM_S3] = (!f64 && d.splits == 3) ? perm_wg : 0;
+  P.wg[S_PERM_S2] = d.pfmt == PLANES_F16_F16 ? perm_wg : 0;
+  P.wg[S_PERM_S3] = d.pfmt == PLANES_F16_E4M3 ? perm_wg : 0;
   P.wg[S_PSTAT] = d.B_pad / 64;
   return P;
 }
@@ -391,7 +391,6 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   if (fork) (void)hipStreamWaitEvent(st, fork->done, 0);
   begin(5, st);
   launch_perm(0, total(S_PERM_F64), st, D, offs(S_PERM_F64), n, nullptr);
-  launch_perm(1, total(S_PERM_S1), st, D, offs(S_PERM_S1), n, nullptr);
   launch_perm(2, total(S_PERM_S2), st, D, offs(S_PERM_S2), n, nullptr);
   launch_perm(3, total(S_PERM_S3), st, D, offs(S_PERM_S3), n, nullptr);
   end(5, st);

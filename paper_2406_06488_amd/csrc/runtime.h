@@ -40,7 +40,7 @@ inline int64_t perm_units(const TestDesc& d, int pcn) {
 // Launch slots: one prefix array of workgroup counts per slot.
 enum Slot {
   S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16, S_MEMBER, S_ROWSUM,
-  S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S1, S_PERM_S2, S_PERM_S3, S_PSTAT, S_COUNT
+  S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S2, S_PERM_S3, S_PSTAT, S_COUNT
 };
 
 // Buffer ids inside one test's region.

@@ -392,7 +392,7 @@ void run_scheduler(etest_server* S) {
         S->h_pcr[2 * k] = q->pc_done;
         S->h_pcr[2 * k + 1] = take;
         const int64_t units = perm_units(P.d, take);
-        for (int s : {S_PERM_F64, S_PERM_S1, S_PERM_S2, S_PERM_S3})
+        for (int s : {S_PERM_F64, S_PERM_S2, S_PERM_S3})
           if (P.wg[s] > 0) w[s] = units;
         q->pc_done += take;
         if (q->pc_done == q->pc_total) {
@@ -435,7 +435,6 @@ void run_scheduler(etest_server* S) {
         launch_center(false, total(S_CENTER_SPLIT), st, D, offs(S_CENTER_SPLIT), R);
       }
       launch_perm(0, total(S_PERM_F64), st, D, offs(S_PERM_F64), R, S->d_pcr);
-      launch_perm(1, total(S_PERM_S1), st, D, offs(S_PERM_S1), R, S->d_pcr);
       launch_perm(2, total(S_PERM_S2), st, D, offs(S_PERM_S2), R, S->d_pcr);
       launch_perm(3, total(S_PERM_S3), st, D, offs(S_PERM_S3), R, S->d_pcr);
       if (total(SEL_FINISH) > 0) {

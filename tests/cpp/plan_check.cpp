@@ -51,7 +51,7 @@ static void check_plan(const etest_request& r, bool internal) {
   size_t need[B_NBUF] = {};
   need[B_W] = (size_t)npad * d0.p_pad * (f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2));
   need[B_D] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 4);
-  need[B_PLANES] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 2 * d0.splits);
+  need[B_PLANES] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : plane_bytes_per_entry(d0.pfmt));
   need[B_Z] = (size_t)d0.nt * TILE_WORDS * d0.B_pad * 4;
   need[B_PART] = (size_t)d0.n_rowk * d0.B_pad * 8;
   need[B_PSTAT] = (size_t)d0.B_pad * 8;
