@@ -50,8 +50,8 @@ enum Buf { B_COLPART, B_COLMEAN, B_W, B_NRM, B_D, B_TSUM, B_TMAX, B_RSUM, B_OBS,
 struct TestPlan {
   TestDesc d{};              // sizes now, pointers once the workspace is placed
   size_t bytes = 0;          // workspace bytes of this test
-  size_t off[16] = {};       // offsets of its buffers inside its region
-  size_t size[16] = {};      // their sizes in bytes
+  size_t off[B_NBUF] = {};   // offsets of its buffers inside its region
+  size_t size[B_NBUF] = {};  // their sizes in bytes
   bool internal_perm = false;  // per-split output lives in the region (off[B_PERMOUT])
   int partner = -1;          // ED test: index of the MMD test whose blocks its Gram writes
   bool share_z = false;      // ... and whose split stream it provides

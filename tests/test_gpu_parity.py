@@ -73,6 +73,7 @@ CASES = [
     (7, 1, 2, 40, 6, 8, 0.5),
     (1, 1, 4, 20, 7, 9, 1.0),
     (40, 33, 1, 300, 8, 10, 0.2),        # p = 1
+    (300, 170, 1030, 400, 9, 11, 0.1),   # FP32: Gram split over K (17 + 16 slices)
 ]
 
 
@@ -198,7 +199,7 @@ def test_graph_replay_with_new_inputs(prec):
 def test_batch_equals_alone():
     specs = [(120, 90, 20, 300, "ed", "f32"), (60, 200, 100, 500, "mmd", "bf16r"),
              (300, 170, 37, 257, "ed", "f64"), (5, 4, 3, 100, "mmd", "f32"),
-             (700, 650, 64, 1000, "ed", "bf16r")]
+             (700, 650, 64, 1000, "ed", "bf16r"), (300, 170, 1030, 300, "ed", "f32")]
     reqs, keep, alone = [], [], []
     for t, (nx, ny, p, B, kind, prec) in enumerate(specs):
         X, Y = _data(nx, ny, p, 100 + t, prec)
@@ -216,17 +217,17 @@ def test_batch_equals_alone():
             assert torch.equal(keep[3 * t + 2], alone[t]["perm_stats"]), (rep, t)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16r"])
-def test_shared_block_stage_equals_alone(prec):
+@pytest.mark.parametrize("prec,p", [("f32", 70), ("bf16r", 70), ("f32", 1030)])
+def test_shared_block_stage_equals_alone(prec, p):
     """An ED and an MMD test on the same X, Y in one batch share staging and Gram (the ED
     test's epilogue writes the kernel blocks too), and with the same seed and B also the
     split stream; each result must equal its run alone, bit for bit, also when the MMD
     test comes first."""
-    X, Y = _data(260, 190, 70, 41, prec, 0.2)
-    X2, Y2 = _data(260, 190, 70, 42, prec, 0.2)
+    X, Y = _data(260, 190, p, 41, prec, 0.2)
+    X2, Y2 = _data(260, 190, p, 42, prec, 0.2)
     Xd, Yd, X2d, Y2d = _dev(X, prec), _dev(Y, prec), _dev(X2, prec), _dev(Y2, prec)
     specs = [("mmd", Xd, Yd, 11), ("ed", Xd, Yd, 12), ("mmd", X2d, Y2d, 13), ("ed", X2d, Y2d, 13)]
-    B, gamma = 700, 1.0 / 70
+    B, gamma = 700, 1.0 / p
     reqs, outs_ps, alone = [], [], []
     for kind, A, Bm, seed in specs:
         ps = torch.zeros(B, dtype=torch.float64, device=DEV)
