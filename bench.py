@@ -105,6 +105,8 @@ def roofline(stage_ms, tests, prec, workload=None, gram_tests=None):
     Gram products one launch of the block stage computes (default: the same tests; an ED
     and an MMD test on the same data share one Gram)."""
     gram_tests = tests if gram_tests is None else gram_tests
+    # the Gram variant that also writes a partner test's blocks runs when tests share one
+    dual = "true" if len(tests) > len(gram_tests) else "false"
     gflops = sum(gram_flops(nx, ny, p) for nx, ny, p, B in gram_tests)
     upd = sum(packed_pairs(nx, ny) * B for nx, ny, p, B in tests)
     if not stage_ms.get("blocks") or not stage_ms.get("resampling"):
@@ -116,14 +118,15 @@ def roofline(stage_ms, tests, prec, workload=None, gram_tests=None):
             r = {"bound": "alu", "achieved": res_tf, "peak": PEAK["fp64_TF"], "unit": "TFLOP/s"}
         else:
             r = {"bound": "mfma", "achieved": res_tf, "peak": PEAK["fp16_TF"], "unit": "TFLOP/s"}
-        r["kernel"] = "k_perm_f64" if prec == "f64" else "k_perm_mfma"
+        r["kernel"] = {"f64": "k_perm_f64", "f32": "k_perm_mfma<2>", "bf16r": "k_perm_mfma<3>"}[prec]
         r["algorithmic"] = ("2 flops per (distinct off-diagonal block entry, split) = %.4g per "
                             "launch" % (2 * upd))
     else:
         peak = {"f64": PEAK["fp64_TF"], "f32": PEAK["fp32_TF"], "bf16r": PEAK["bf16_TF"]}[prec]
         r = {"bound": "alu" if prec == "f64" else "mfma", "achieved": gram_tf, "peak": peak,
              "unit": "TFLOP/s",
-             "kernel": {"f64": "k_dist_f64", "f32": "k_gram_f32", "bf16r": "k_gram_bf16"}[prec],
+             "kernel": {"f64": "k_dist_f64", "f32": "k_gram_f32<%s>" % dual,
+                        "bf16r": "k_gram_bf16<%s>" % dual}[prec],
              "algorithmic": "2p flops per distinct Gram entry = %.4g per launch" % gflops}
     r["frac"] = r["achieved"] / r["peak"]
     r["traffic"] = measured_traffic(r["kernel"], workload) if workload else None
@@ -158,7 +161,7 @@ def measured_traffic(kernel, workload):
     except (OSError, ValueError):
         return None
     e = table.get("%s|%s" % (kernel, workload))
-    if not e or e.get("source_sha256") != source_hash(kernel):
+    if not e or e.get("source_sha256") != source_hash(kernel.split("<")[0]):
         return None
     return e["fetch_bytes"] + e["write_bytes"]
 
