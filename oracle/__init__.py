@@ -54,6 +54,8 @@ def lib():
         L.orc_threshold.argtypes = [ctypes.c_int, dp, dp, dp, i64, i64, dp]
         L.orc_test.argtypes = [ctypes.c_int, dp, i64, dp, i64, i64, ctypes.c_double, i64,
                                ctypes.c_uint64, dp, dp, dp, i64p, dp, ctypes.c_int]
+        L.orc_cross.argtypes = [ctypes.c_int, dp, i64, dp, i64, i64, ctypes.c_double, dp,
+                                ctypes.c_int]
         _lib = L
     return _lib
 
@@ -184,3 +186,17 @@ def run_test(X, Y, B, seed, kind=ED, gamma=1.0, nthreads=0):
         raise ValueError("oracle test failed with code %d" % r)
     return dict(statistic=so.value, threshold=thr.value, count_ge=cnt.value, p_value=pv.value,
                 perm_stats=ps[:B].copy())
+
+
+def cross(X, Y, kind=ED, gamma=1.0, nthreads=0):
+    """Cross-MMD (Alg. 6) or cross-ED (Alg. 7) test: dict(statistic=U, sigma, z, p_value)."""
+    X, Y = _f64(X), _f64(Y)
+    if X.shape[1] != Y.shape[1]:
+        raise ValueError("cross: X and Y need the same number of columns")
+    out = np.empty(4, dtype=np.float64)
+    r = lib().orc_cross(kind, _d(X), X.shape[0], _d(Y), Y.shape[0], X.shape[1], gamma, _d(out),
+                        nthreads)
+    if r:
+        raise ValueError("cross: invalid arguments (nx, ny >= 2, p >= 1, gamma > 0 for MMD)")
+    return {"statistic": float(out[0]), "sigma": float(out[1]), "z": float(out[2]),
+            "p_value": float(out[3])}

@@ -393,3 +393,86 @@ done:
   if (ps != perm_stats) free(ps);
   return r;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Cross-MMD test (Alg. 6) and cross-ED test (Alg. 7), appendix "The cross-ED  */
+/* test".  x is cut into x1 (its first floor(nx/2) rows) and x2 (the rest), y  */
+/* likewise; the four cross blocks come from orc_block (direct differences).   */
+/*   MMD: U_x = mean K(x1,x2) - mean K(x1,y2),  U_y = mean K(y1,x2) - mean K(y1,y2) */
+/*   ED:  U_x = mean D(x1,y2) - mean D(x1,x2),  U_y = mean D(y1,y2) - mean D(y1,x2) */
+/*   U = U_x - U_y;  s_x = mean over x1 rows of (row mean difference - U_x)^2,     */
+/*   s_y likewise over y1 rows;  sigma = sqrt(s_x / nx1 + s_y / ny1);              */
+/*   p = 1 - Phi(U / sigma), written as erfc(z / sqrt 2) / 2 so that the upper     */
+/*   tail keeps its digits.  Every mean is an exactly rounded sum (orc_xsum)        */
+/*   divided by its count.                                                          */
+/* Reading: sigma = 0 gives z = +inf, -inf or 0 by the sign of U (p = 0, 1, 1/2).   */
+/* out[0] = U, out[1] = sigma, out[2] = z, out[3] = p.                               */
+/* ------------------------------------------------------------------------- */
+static double mean_of(const double* v, int64_t n) { return orc_xsum(v, n) / (double)n; }
+
+/* mean over the rows of (row mean of A - row mean of B - u)^2; A is rows x na, B rows x nb */
+static double row_spread(const double* A, int64_t na, const double* Bm, int64_t nb, int64_t rows,
+                         double u) {
+  double* d2 = (double*)malloc(sizeof(double) * (size_t)rows);
+  if (!d2) return NAN;
+  for (int64_t i = 0; i < rows; i++) {
+    double f = mean_of(A + i * na, na) - mean_of(Bm + i * nb, nb) - u;
+    d2[i] = f * f;
+  }
+  double s = mean_of(d2, rows);
+  free(d2);
+  return s;
+}
+
+int orc_cross(int kind, const double* X, int64_t nx, const double* Y, int64_t ny, int64_t p,
+              double gamma, double out[4], int nthreads) {
+  if (nx < 2 || ny < 2 || p < 1) return 1;
+  if (kind == ORC_MMD && !(gamma > 0.0)) return 1;
+  const int64_t nx1 = nx / 2, nx2 = nx - nx1, ny1 = ny / 2, ny2 = ny - ny1;
+  const double* x1 = X;
+  const double* x2 = X + nx1 * p;
+  const double* y1 = Y;
+  const double* y2 = Y + ny1 * p;
+  double* KX1X2 = (double*)malloc(sizeof(double) * (size_t)(nx1 * nx2));
+  double* KY1Y2 = (double*)malloc(sizeof(double) * (size_t)(ny1 * ny2));
+  double* KX1Y2 = (double*)malloc(sizeof(double) * (size_t)(nx1 * ny2));
+  double* KY1X2 = (double*)malloc(sizeof(double) * (size_t)(ny1 * nx2));
+  int r = 0;
+  if (!KX1X2 || !KY1Y2 || !KX1Y2 || !KY1X2) {
+    r = 3;
+    goto done;
+  }
+  orc_block(x1, nx1, x2, nx2, p, kind, gamma, KX1X2, nthreads);
+  orc_block(y1, ny1, y2, ny2, p, kind, gamma, KY1Y2, nthreads);
+  orc_block(x1, nx1, y2, ny2, p, kind, gamma, KX1Y2, nthreads);
+  orc_block(y1, ny1, x2, nx2, p, kind, gamma, KY1X2, nthreads);
+  {
+    /* the block whose mean enters with + and the one with -, for x1 rows and y1 rows */
+    const int ed = kind == ORC_ED;
+    const double* xa = ed ? KX1Y2 : KX1X2;
+    const double* xb = ed ? KX1X2 : KX1Y2;
+    const int64_t na = ed ? ny2 : nx2, nb = ed ? nx2 : ny2;
+    const double* ya = ed ? KY1Y2 : KY1X2;
+    const double* yb = ed ? KY1X2 : KY1Y2;
+    const int64_t ma = ed ? ny2 : nx2, mb = ed ? nx2 : ny2;
+    const double ux = mean_of(xa, nx1 * na) - mean_of(xb, nx1 * nb);
+    const double uy = mean_of(ya, ny1 * ma) - mean_of(yb, ny1 * mb);
+    const double u = ux - uy;
+    const double sx = row_spread(xa, na, xb, nb, nx1, ux);
+    const double sy = row_spread(ya, ma, yb, mb, ny1, uy);
+    const double sigma = sqrt(sx / (double)nx1 + sy / (double)ny1);
+    double z;
+    if (sigma > 0.0) z = u / sigma;
+    else z = u > 0.0 ? INFINITY : (u < 0.0 ? -INFINITY : 0.0);
+    out[0] = u;
+    out[1] = sigma;
+    out[2] = z;
+    out[3] = 0.5 * erfc(z / sqrt(2.0));
+  }
+done:
+  free(KX1X2);
+  free(KY1Y2);
+  free(KX1Y2);
+  free(KY1X2);
+  return r;
+}

@@ -415,3 +415,114 @@ def test_distance_blocks_against_scipy():
     D = oracle.block(P, P)
     assert D[0, 1] == 5.0 and D[0, 2] == 13.0 and D[0, 3] == 17.0 and D[1, 1] == 0.0
     assert np.array_equal(D, D.T)
+
+
+# --------------------------------------------------------------------------- cross tests
+
+def _h_quadruple_mean(X, Y, kind, gamma):
+    """The cross statistic by its definition: the mean over all index quadruples
+    (i in x1, i' in x2, j in y1, j' in y2) of h_K (cross-MMD) or h_D (cross-ED), written as
+    plain loops over pairwise distances from scipy (no block means)."""
+    nx1, ny1 = X.shape[0] // 2, Y.shape[0] // 2
+    x1, x2, y1, y2 = X[:nx1], X[nx1:], Y[:ny1], Y[ny1:]
+    d = lambda A, B: cdist(A, B)  # noqa: E731
+    k = (lambda A, B: d(A, B)) if kind == ED else (lambda A, B: np.exp(-gamma * d(A, B) ** 2))
+    kx1x2, kx1y2, ky1x2, ky1y2 = k(x1, x2), k(x1, y2), k(y1, x2), k(y1, y2)
+    total, count = [], 0
+    for i in range(len(x1)):
+        for ip in range(len(x2)):
+            for j in range(len(y1)):
+                for jp in range(len(y2)):
+                    if kind == ED:  # D(x_i, y_j') - D(x_i, x_i') - D(y_j, y_j') + D(y_j, x_i')
+                        h = kx1y2[i, jp] - kx1x2[i, ip] - ky1y2[j, jp] + ky1x2[j, ip]
+                    else:  # K(x_i, x_i') - K(x_i, y_j') - K(y_j, x_i') + K(y_j, y_j')
+                        h = kx1x2[i, ip] - kx1y2[i, jp] - ky1x2[j, ip] + ky1y2[j, jp]
+                    total.append(h)
+                    count += 1
+    return math.fsum(total) / count
+
+
+@pytest.mark.parametrize("kind", [ED, MMD])
+@pytest.mark.parametrize("nx,ny", [(4, 5), (7, 6), (2, 9)])
+def test_cross_statistic_is_the_quadruple_mean(kind, nx, ny):
+    """Appendix, cross-ED test: the statistic U of Alg. 6 / Alg. 7 (differences of block
+    means) equals the V-statistic of h over all quadruples (brute force on tiny inputs)."""
+    g = _rng(300 + nx * 10 + ny)
+    X, Y = g.standard_normal((nx, 3)), g.standard_normal((ny, 3)) + 0.4
+    gamma = 0.3
+    got = oracle.cross(X, Y, kind, gamma)["statistic"]
+    want = _h_quadruple_mean(X, Y, kind, gamma)
+    assert abs(got - want) <= 1e-13 * max(1.0, abs(want))
+
+
+@pytest.mark.parametrize("kind", [ED, MMD])
+def test_cross_swap_symmetry_and_identical_samples(kind):
+    """Swapping x and y leaves U, sigma and p unchanged (U_x and U_y trade places with
+    their signs flipped); with y = x every block pair cancels row by row: U = 0, sigma = 0,
+    and by the reading for sigma = 0, z = 0 and p = 1/2."""
+    g = _rng(41)
+    X, Y = g.standard_normal((31, 4)), g.standard_normal((26, 4)) * 1.3
+    a, b = oracle.cross(X, Y, kind, 0.2), oracle.cross(Y, X, kind, 0.2)
+    for k in ("statistic", "sigma", "p_value"):
+        assert abs(a[k] - b[k]) <= 1e-13 * max(1.0, abs(a[k])), k
+    same = oracle.cross(X, X.copy(), kind, 0.2)
+    assert same["statistic"] == 0.0 and same["sigma"] == 0.0 and same["p_value"] == 0.5
+
+
+def test_cross_ed_equals_cross_mmd_form_on_distances():
+    """The paper's remark closing the cross-ED appendix: the cross-ED test is Alg. 6 with
+    the four distance blocks in place of the kernel blocks and p = 1 - Phi(-U/sigma).
+    That form is computed here from the oracle's distance blocks; its U is the negative
+    of Alg. 7's, its sigma the same, and its p-value equal."""
+    from scipy.stats import norm
+    g = _rng(52)
+    X, Y = g.standard_normal((45, 6)), g.standard_normal((38, 6)) + 0.25
+    nx1, ny1 = 22, 19
+    x1, x2, y1, y2 = X[:nx1], X[nx1:], Y[:ny1], Y[ny1:]
+    b = lambda A, B: oracle.block(A, B, ED)  # noqa: E731
+    kx1x2, ky1y2, kx1y2, ky1x2 = b(x1, x2), b(y1, y2), b(x1, y2), b(y1, x2)
+    ux = kx1x2.mean() - kx1y2.mean()
+    uy = ky1x2.mean() - ky1y2.mean()
+    u = ux - uy
+    sx = np.mean((kx1x2.mean(1) - kx1y2.mean(1) - ux) ** 2)
+    sy = np.mean((ky1x2.mean(1) - ky1y2.mean(1) - uy) ** 2)
+    sigma = math.sqrt(sx / nx1 + sy / ny1)
+    p = norm.sf(-u / sigma)
+    o = oracle.cross(X, Y, ED)
+    assert abs(o["statistic"] + u) <= 1e-12 * abs(u)
+    assert abs(o["sigma"] - sigma) <= 1e-12 * sigma
+    assert abs(o["p_value"] - p) <= 1e-12 * max(p, 1e-300)
+
+
+def test_cross_p_value_is_the_normal_upper_tail():
+    """p = 1 - Phi(z) (Alg. 6 / Alg. 7 last line) against scipy's normal survival function,
+    including far tails, where 1 - Phi would lose every digit."""
+    from scipy.stats import norm
+    g = _rng(63)
+    for shift in (0.0, 0.05, 0.2, 0.6, 1.5, -0.3):
+        X, Y = g.standard_normal((80, 5)), g.standard_normal((70, 5)) + shift
+        for kind in (ED, MMD):
+            o = oracle.cross(X, Y, kind, 0.2)
+            assert abs(o["z"] - o["statistic"] / o["sigma"]) <= 1e-15 * abs(o["z"]) + 1e-300
+            want = norm.sf(o["z"])
+            assert abs(o["p_value"] - want) <= 1e-12 * want, (shift, kind, o, want)
+
+
+def test_cross_null_p_values_are_roughly_uniform():
+    """Under the null the studentised statistic is asymptotically N(0, 1) (the reason the
+    cross tests need no permutations), so p-values over many null replications are close
+    to uniform (a loose Kolmogorov-Smirnov check)."""
+    from scipy.stats import kstest
+    g = _rng(74)
+    ps = []
+    for rep in range(300):
+        X, Y = g.standard_normal((60, 3)), g.standard_normal((60, 3))
+        ps.append(oracle.cross(X, Y, ED)["p_value"])
+    assert kstest(ps, "uniform").pvalue > 1e-3
+
+
+def test_cross_rejects_too_few_rows():
+    with pytest.raises(ValueError):
+        oracle.cross(np.zeros((1, 3)), np.zeros((4, 3)), ED)
+    with pytest.raises(ValueError):
+        oracle.cross(np.zeros((4, 3)), np.zeros((4, 3)), MMD, 0.0)
