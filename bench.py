@@ -360,6 +360,57 @@ def run_batched(args):
     return line
 
 
+def run_cross(args):
+    """Cross-ED test (permutation-free, the paper's Alg. 7) on the plain_f32 data (FP32) or
+    the precision_bf16 data (BF16-refined): tests/s, and the cross blocks' Gram rate."""
+    import numpy as np
+
+    from paper_2406_06488_amd import api, inputs
+    wl = inputs.plain_f32() if args.workload == "cross_f32" else inputs.precision_bf16()
+    prec = "f32" if args.workload == "cross_f32" else "bf16r"
+    X, Y = wl.data()
+    Xd, Yd = to_dev(X, Y, prec)
+    nx1, ny1 = wl.nx // 2, wl.ny // 2
+    rows, cols = nx1 + ny1, wl.nx + wl.ny - nx1 - ny1
+    name = "cross_ed_%s_%dx%dx%d" % (prec, wl.nx, wl.ny, wl.p)
+    log("workload", name, "steps", args.steps, "warmup", args.warmup)
+
+    def step():
+        return api.cross(Xd, Yd, "ed", prec)
+
+    elapsed, live, prof, res = timed(step, args.steps, args.warmup)
+    stage = per_launch(prof)
+    stage.update({k: v for k, v in per_launch(live).items() if k in LIVE_STAGES})
+    flops = 2.0 * wl.p * rows * cols  # every cross pair once: no symmetry to use
+    gram_tf = flops / (stage["blocks"] * 1e-3) / 1e12
+    peak = PEAK["fp32_TF"] if prec == "f32" else PEAK["bf16_TF"]
+    kernel = "k_gram_f32<false>" if prec == "f32" else "k_gram_bf16<false>"
+    line = base_line(args, name, args.steps / elapsed, elapsed, args.steps,
+                     "f32" if prec == "f32" else "bf16",
+                     {"nx": wl.nx, "ny": wl.ny, "p": wl.p, "statistic": "cross-ed",
+                      "precision": prec})
+    line.update({"metric": "cross-ED tests/s", "unit": "tests/s", "gram_tflops": gram_tf,
+                 "stage_ms": {k: round(v, 5) for k, v in stage.items()},
+                 "stage_ms_live": [k for k in LIVE_STAGES if k in stage],
+                 "result": res,
+                 "roofline": {"bound": "mfma", "achieved": gram_tf, "peak": peak,
+                              "unit": "TFLOP/s", "kernel": kernel,
+                              "algorithmic": "2p flops per cross pair = %.4g per launch" % flops,
+                              "frac": gram_tf / peak, "traffic": measured_traffic(kernel, name)}})
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle) ...")
+        t0 = time.perf_counter()
+        oracle.cross(X.astype(np.float64), Y.astype(np.float64), oracle.ED)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "tests/s",
+                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+                                "kind": "oracle", "sample": "%s: one whole test" % name}
+    else:
+        line["cpu_baseline"] = None
+    return line
+
+
 def run_serving(args):
     import numpy as np
     import torch
@@ -456,7 +507,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_f32",
-                    choices=["plain_f32", "small_f64", "precision_bf16", "batched", "serving"])
+                    choices=["plain_f32", "small_f64", "precision_bf16", "batched", "serving",
+                             "cross_f32", "cross_bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=200.0)
@@ -479,6 +531,8 @@ def main():
         line = run_single(args)
     elif args.workload == "batched":
         line = run_batched(args)
+    elif args.workload.startswith("cross"):
+        line = run_cross(args)
     else:
         line = run_serving(args)
     print(json.dumps(line), flush=True)

@@ -135,6 +135,25 @@ etest_status etest_run(const etest_request* req, void* stream, etest_result* out
 etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* stream);
 etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void* stream);
 
+/* ---- Cross tests (permutation-free; the paper's appendix on the cross-ED test) ---- */
+
+typedef struct {
+  double statistic; /* U = U_x - U_y: cross-MMD (Alg. 6) or cross-ED (Alg. 7) statistic       */
+  double sigma;     /* studentising scale sqrt(s_x / nx1 + s_y / ny1)                          */
+  double z;         /* U / sigma (+inf, -inf or 0 by the sign of U when sigma == 0)            */
+  double p_value;   /* 1 - Phi(z)                                                              */
+  int64_t n_refined;/* pairs recomputed by direct difference (BF16 form; 0 otherwise)          */
+} etest_cross_result;
+
+/* Cross-MMD / cross-ED test on device buffers, synchronous on `stream`.  x is cut into x1
+   (its first floor(nx/2) rows) and x2 (the rest), y likewise; the four cross blocks
+   K(x1,x2), K(y1,y2), K(x1,y2), K(y1,x2) (or distances) are computed on MFMA (FP32 / BF16
+   forms, as for the blocks of a permutation test) or by direct FP64 differences, reduced
+   to per-row means in FP64 and never stored.  req: kind, prec, nx, ny (both >= 2), p,
+   gamma (MMD), X and Y as for etest_run; B, seed and perm_stats are ignored.  Errors:
+   EINVAL (arguments), ENONFINITE (NaN / Inf input; out untouched), ENOMEM, EDEVICE. */
+etest_status etest_cross(const etest_request* req, void* stream, etest_cross_result* out);
+
 /* n independent tests in one batched pass: every stage is one launch covering all tests,
    and the launch sequence is captured once into a HIP graph and replayed while the same
    request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,

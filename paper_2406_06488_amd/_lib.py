@@ -23,6 +23,14 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CrossResult(ctypes.Structure):
+    _fields_ = [("statistic", c_dbl), ("sigma", c_dbl), ("z", c_dbl), ("p_value", c_dbl),
+                ("n_refined", c_i64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Request(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("prec", c_i32), ("nx", c_i64), ("ny", c_i64), ("p", c_i64),
                 ("B", c_i64), ("seed", c_u64), ("gamma", c_dbl), ("X", c_vp), ("Y", c_vp),
@@ -45,6 +53,7 @@ SIGNATURES = [
     ("mmd_test_f64", c_i32, [c_vp, c_i64, c_vp, c_i64, c_i64, c_dbl, c_i64, c_u64, c_vp,
                              ctypes.POINTER(Result)]),
     ("etest_run", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
+    ("etest_cross", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(CrossResult)]),
     ("ed_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("mmd_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("etest_batch", c_i32, [ctypes.POINTER(Request), c_i64, c_vp, ctypes.POINTER(Result)]),

@@ -111,6 +111,16 @@ def run(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True):
     return out
 
 
+def cross(X, Y, kind="ed", prec="f32", gamma=0.0):
+    """Cross-ED / cross-MMD test (permutation-free) on device tensors, synchronous.
+    Returns dict(statistic, sigma, z, p_value, n_refined)."""
+    _check_dev(X, Y, prec)
+    req = make_request(X, Y, 0, 0, kind, prec, gamma, None)
+    r = _lib.CrossResult()
+    check(_lib.load().etest_cross(ctypes.byref(req), _stream(), ctypes.byref(r)))
+    return r.as_dict()
+
+
 def run_async(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stats=None):
     """Enqueue one test on torch's current stream; returns a device buffer holding the
     etest_result (6 x 8 bytes).  Use result_from_device() after synchronising."""

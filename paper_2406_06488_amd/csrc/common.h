@@ -92,7 +92,27 @@ struct TestDesc {
   float* ptmax;
   int32_t* pflags;
   double pgamma;
+  // Cross tests (cross-MMD / cross-ED): x and y are cut in halves and staged as the
+  // "x side" [x1; y1] (nx = cnx1 + cny1 rows) and the "y side" [x2; y2]; only the
+  // rectangle of tiles x side by y side is computed, and each tile keeps its row sums over
+  // the x2 columns and over the y2 columns apart.
+  int32_t cross, cnx1, cny1, cnx2;
 };
+
+// Input row t of the pooled sample, in staging order: x rows then y rows; for a cross
+// test x1, y1, x2, y2.
+template <typename T>
+__device__ inline const T* pooled_row(const TestDesc& d, int64_t t) {
+  const T* X = (const T*)d.X;
+  const T* Y = (const T*)d.Y;
+  if (!d.cross) return t < d.nx ? X + t * d.p : Y + (t - d.nx) * d.p;
+  if (t < d.cnx1) return X + t * d.p;
+  t -= d.cnx1;
+  if (t < d.cny1) return Y + t * d.p;
+  t -= d.cny1;
+  if (t < d.cnx2) return X + (d.cnx1 + t) * d.p;
+  return Y + (d.cny1 + t - d.cnx2) * d.p;
+}
 
 // Workgroups of a launch are dealt to the 8 XCDs in turn (workgroup b on XCD b % 8), and
 // each XCD has its own L2.  xcd_grouped renumbers them so that every XCD works through

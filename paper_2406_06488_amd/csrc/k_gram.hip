@@ -27,7 +27,12 @@ struct TileCtx {
 __device__ inline TileCtx tile_ctx(const TestDesc& d, int64_t local) {
   TileCtx c;
   c.t = (int)local;
-  tile_coords(c.t, d.nt, &c.i, &c.j);
+  if (d.cross) {  // the rectangle x side by y side, row-major
+    c.i = (int)(local / d.ty);
+    c.j = d.tx + (int)(local % d.ty);
+  } else {
+    tile_coords(c.t, d.nt, &c.i, &c.j);
+  }
   c.rows_i = tile_rows(d, c.i);
   c.rows_j = tile_rows(d, c.j);
   c.diag = c.i == c.j;
@@ -36,8 +41,8 @@ __device__ inline TileCtx tile_ctx(const TestDesc& d, int64_t local) {
 
 // Input row (pooled, unpadded) of tile row r of pooled tile i.
 __device__ inline const float* input_row_f32(const TestDesc& d, int i, int r) {
-  if (i < d.tx) return (const float*)d.X + ((int64_t)i * TILE + r) * d.p;
-  return (const float*)d.Y + ((int64_t)(i - d.tx) * TILE + r) * d.p;
+  const int64_t t = i < d.tx ? (int64_t)i * TILE + r : d.nx + (int64_t)(i - d.tx) * TILE + r;
+  return pooled_row<float>(d, t);
 }
 
 // d^2 -> stored block value (distance, or Gaussian kernel with bandwidth 1 / gamma);
@@ -54,18 +59,27 @@ __device__ inline float block_value_f32(int kind, double gamma, const TileCtx& c
 // feeds (shared block stage).
 struct BlockOut {
   int kind;
+  int split;  // cross tests: y-side columns below `split` are x2, the rest y2; -1 otherwise
   double gamma;
   float* D;
   double* tsum;
   float* tmax;
 };
-__device__ inline BlockOut own_out(const TestDesc& d, int t) {
-  return BlockOut{d.kind, d.gamma, (float*)d.D + (int64_t)t * TILE * TILE,
-                  d.tsum + (int64_t)t * TSUM_STRIDE, d.tmax + (int64_t)t * TMAX_PER_TILE};
+// columns of y-side tile j that hold x2 rows (cross tests)
+__device__ inline int cross_split(const TestDesc& d, int j) {
+  const int s = d.cnx2 - (j - d.tx) * TILE;
+  return s < 0 ? 0 : (s > TILE ? TILE : s);
 }
-__device__ inline BlockOut partner_out(const TestDesc& d, int t) {
-  return BlockOut{KIND_MMD, d.pgamma, (float*)d.pD + (int64_t)t * TILE * TILE,
-                  d.ptsum + (int64_t)t * TSUM_STRIDE, d.ptmax + (int64_t)t * TMAX_PER_TILE};
+__device__ inline BlockOut own_out(const TestDesc& d, const TileCtx& c) {
+  const int64_t t = c.t;
+  return BlockOut{d.kind, d.cross ? cross_split(d, c.j) : -1, d.gamma,
+                  d.cross ? nullptr : (float*)d.D + t * TILE * TILE,
+                  d.tsum + t * TSUM_STRIDE, d.tmax + t * TMAX_PER_TILE};
+}
+__device__ inline BlockOut partner_out(const TestDesc& d, const TileCtx& c) {
+  const int64_t t = c.t;
+  return BlockOut{KIND_MMD, -1, d.pgamma, (float*)d.pD + t * TILE * TILE,
+                  d.ptsum + t * TSUM_STRIDE, d.ptmax + t * TMAX_PER_TILE};
 }
 
 constexpr int HALF = TILE / 2;
@@ -83,6 +97,30 @@ constexpr int TILE_LDS = TILE + 4;
 //  store: float4 reads of whole rows (32 lanes per row), coalesced float4 stores.
 __device__ inline void emit_half(const BlockOut& o, int half, const float* tl, float& vmax) {
   const int tid = threadIdx.x;
+  if (o.split >= 0) {
+    // cross tests: each row's sums over the x2 columns and over the y2 columns, kept apart
+    // (tsum[r] and tsum[TILE + r]); the tile itself is not stored
+    const int row = tid >> 2, q = tid & 3;
+    const float* src = tl + row * TILE_LDS + q * 32;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) {
+      const int col = q * 32 + ((k + q) & 31);
+      const float x = src[(k + q) & 31];
+      if (col < o.split) s0 += (double)x;
+      else s1 += (double)x;
+      vmax = fmaxf(vmax, fabsf(x));
+    }
+    s0 += __shfl_xor(s0, 1, 64);
+    s0 += __shfl_xor(s0, 2, 64);
+    s1 += __shfl_xor(s1, 1, 64);
+    s1 += __shfl_xor(s1, 2, 64);
+    if (q == 0) {
+      o.tsum[half * HALF + row] = s0;
+      o.tsum[TILE + half * HALF + row] = s1;
+    }
+    return;
+  }
   {
     const int row = tid >> 2, q = tid & 3;
     const float* src = tl + row * TILE_LDS + q * 32;
@@ -321,11 +359,11 @@ k_gram_f32(const TestDesc* __restrict__ descs,
   // outputs; plain launches turn them into block values at once
   if (DUAL) {
     gram_epilogue<false>(d, c, acc, wm, wn, h, lr);
-    finish_tile<true>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
+    finish_tile<true>(c, smem, acc, wm, wn, h, lr, own_out(d, c), partner_out(d, c),
                       d.pD != nullptr);
   } else {
     gram_epilogue<true>(d, c, acc, wm, wn, h, lr);
-    const BlockOut o = own_out(d, c.t);
+    const BlockOut o = own_out(d, c);
     finish_tile<false>(c, smem, acc, wm, wn, h, lr, o, o, false);
   }
 }
@@ -407,11 +445,11 @@ k_gram_bf16(const TestDesc* __restrict__ descs,
   // outputs; plain launches turn them into block values at once
   if (DUAL) {
     gram_epilogue<false>(d, c, acc, wm, wn, h, lr);
-    finish_tile<true>(c, smem, acc, wm, wn, h, lr, own_out(d, c.t), partner_out(d, c.t),
+    finish_tile<true>(c, smem, acc, wm, wn, h, lr, own_out(d, c), partner_out(d, c),
                       d.pD != nullptr);
   } else {
     gram_epilogue<true>(d, c, acc, wm, wn, h, lr);
-    const BlockOut o = own_out(d, c.t);
+    const BlockOut o = own_out(d, c);
     finish_tile<false>(c, smem, acc, wm, wn, h, lr, o, o, false);
   }
 }
@@ -454,7 +492,10 @@ __global__ void __launch_bounds__(256) k_dist_f64(const TestDesc* __restrict__ d
         }
     }
   }
-  double* D = (double*)d.D + (int64_t)c.t * TILE * TILE;
+  // cross tests: row sums over the x2 columns (rs) and the y2 columns (cs, in place of the
+  // column sums), no stored tile
+  const int split = d.cross ? cross_split(d, c.j) : -1;
+  double* D = d.cross ? nullptr : (double*)d.D + (int64_t)c.t * TILE * TILE;
   double rs[8], cs[8];
   for (int a = 0; a < 8; ++a) rs[a] = 0.0;
   for (int b = 0; b < 8; ++b) cs[b] = 0.0;
@@ -465,10 +506,30 @@ __global__ void __launch_bounds__(256) k_dist_f64(const TestDesc* __restrict__ d
       if (r >= c.rows_i || col >= c.rows_j) v = 0.0;
       else if (c.diag && r == col) v = d.kind == KIND_ED ? 0.0 : 1.0;
       else v = d.kind == KIND_ED ? sqrt(acc[a][b]) : exp(-d.gamma * acc[a][b]);
-      D[r * TILE + col] = v;
-      rs[a] += v;
-      cs[b] += v;
+      if (split >= 0) {
+        if (col < split) rs[a] += v;
+        else cs[a] += v;
+      } else {
+        D[r * TILE + col] = v;
+        rs[a] += v;
+        cs[b] += v;
+      }
     }
+  if (split >= 0) {
+    for (int a = 0; a < 8; ++a) rp[(tr + 16 * a) * 16 + tc] = rs[a];
+    for (int a = 0; a < 8; ++a) cp[(tr + 16 * a) * 16 + tc] = cs[a];
+    __syncthreads();
+    if (tid < TILE) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int q = 0; q < 16; ++q) {
+        s0 += rp[tid * 16 + q];
+        s1 += cp[tid * 16 + q];
+      }
+      d.tsum[(int64_t)c.t * TSUM_STRIDE + tid] = s0;
+      d.tsum[(int64_t)c.t * TSUM_STRIDE + TILE + tid] = s1;
+    }
+    return;
+  }
   for (int a = 0; a < 8; ++a) rp[(tr + 16 * a) * 16 + tc] = rs[a];
   for (int b = 0; b < 8; ++b) cp[tr * TILE + tc + 16 * b] = cs[b];
   __syncthreads();

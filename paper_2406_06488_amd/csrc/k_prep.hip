@@ -12,10 +12,10 @@ namespace et {
 constexpr int ROWCHUNK = COLSUM_ROWS;
 
 __device__ inline float load_in_f32(const TestDesc& d, int64_t t, int k) {
-  return t < d.nx ? ((const float*)d.X)[t * d.p + k] : ((const float*)d.Y)[(t - d.nx) * d.p + k];
+  return pooled_row<float>(d, t)[k];
 }
 __device__ inline double load_in_f64(const TestDesc& d, int64_t t, int k) {
-  return t < d.nx ? ((const double*)d.X)[t * d.p + k] : ((const double*)d.Y)[(t - d.nx) * d.p + k];
+  return pooled_row<double>(d, t)[k];
 }
 
 // Partial column sums over chunks of ROWCHUNK pooled rows (FP64).  All ROWCHUNK loads of a
@@ -101,9 +101,7 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
     if (lane == 0) ((double*)d.nrm)[pos] = nrm;
   } else {
     const bool bf = d.prec == PREC_BF16R;
-    const float* src = t < 0 ? nullptr
-                             : (t < d.nx ? (const float*)d.X + t * d.p
-                                         : (const float*)d.Y + (t - d.nx) * d.p);
+    const float* src = t < 0 ? nullptr : pooled_row<float>(d, t);
     // four columns per lane when every row starts on a 16-byte boundary
     const bool vec = (d.p & 3) == 0 && (((uintptr_t)d.X | (uintptr_t)d.Y) & 15) == 0;
     if (vec) {

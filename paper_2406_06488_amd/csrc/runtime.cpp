@@ -461,6 +461,9 @@ static void profile_collect() {
           hipEventElapsedTime(&ms, ev->begin[k], ev->end[k]) == hipSuccess) {
         g_prof.ms[k] += ms;
         g_prof.launches[k] += 1;
+      } else {
+        (void)hipGetLastError();  // a stage this pass did not run (e.g. a cross test's
+                                  // resampling): its events were never recorded
       }
     }
     g_prof.spare.push_back(ev);
@@ -920,3 +923,130 @@ etest_status etest_perm_stats_from_membership(const etest_request* req, const ui
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ cross tests
+// One cross test: staging of [x1; y1 | x2; y2], the rectangle of cross tiles with per-row
+// sums split by column class, then the statistic (k_cross.hip).  Synchronous.
+etest_status etest_cross(const etest_request* req, void* stream, etest_cross_result* out) {
+  if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
+  etest_request r = *req;
+  r.B = 0;
+  r.perm_stats = nullptr;
+  etest_status s = validate_request(r);
+  if (s != ETEST_OK) return s;
+  if (r.nx < 2 || r.ny < 2) return set_error(ETEST_EINVAL, "cross tests need nx, ny >= 2");
+  init_pool_once();
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nx1 = r.nx / 2, ny1 = r.ny / 2, nx2 = r.nx - nx1;
+  TestDesc d{};
+  d.kind = r.kind;
+  d.prec = r.prec;
+  d.cross = 1;
+  d.cnx1 = (int32_t)nx1;
+  d.cny1 = (int32_t)ny1;
+  d.cnx2 = (int32_t)nx2;
+  d.nx = (int32_t)(nx1 + ny1);              // x side
+  d.ny = (int32_t)(r.nx + r.ny - nx1 - ny1);  // y side
+  d.p = (int32_t)r.p;
+  const bool f64 = r.prec == ETEST_PREC_F64;
+  const int kq = f64 ? 16 : (r.prec == ETEST_PREC_F32 ? 32 : 64);
+  d.p_pad = (int32_t)((r.p + kq - 1) / kq * kq);
+  d.tx = (d.nx + TILE - 1) / TILE;
+  d.ty = (d.ny + TILE - 1) / TILE;
+  d.nt = d.tx + d.ty;
+  d.ntiles = d.tx * d.ty;
+  d.refine = f64 ? 0 : 1;
+  d.nrowchunks = (int32_t)((r.nx + r.ny + COLSUM_ROWS - 1) / COLSUM_ROWS);
+  d.gamma = r.kind == ETEST_MMD ? r.gamma : 0.0;
+  d.X = r.X;
+  d.Y = r.Y;
+  const int64_t npad = (int64_t)d.nt * TILE;
+  const size_t el_w = f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2);
+  // workspace: descriptor, launch tables, then the buffers the stages index
+  enum { C_DESC, C_OFFS, C_COLPART, C_COLMEAN, C_W, C_NRM, C_TSUM, C_TMAX, C_V, C_OBS, C_FLAGS, C_N };
+  size_t sz[C_N];
+  sz[C_DESC] = sizeof(TestDesc);
+  sz[C_OFFS] = 5 * 2 * sizeof(int64_t);
+  sz[C_COLPART] = f64 ? 0 : (size_t)d.nrowchunks * r.p * 8;
+  sz[C_COLMEAN] = f64 ? 0 : (size_t)r.p * 8;
+  sz[C_W] = (size_t)npad * d.p_pad * el_w;
+  sz[C_NRM] = (size_t)npad * (f64 ? 8 : 4);
+  sz[C_TSUM] = (size_t)d.ntiles * TSUM_STRIDE * 8;
+  sz[C_TMAX] = (size_t)d.ntiles * TMAX_PER_TILE * 4;
+  sz[C_V] = (size_t)npad * 8;
+  sz[C_OBS] = 8 * 8;
+  sz[C_FLAGS] = FLAG_WORDS * 4;
+  size_t off[C_N], total = 0;
+  for (int k = 0; k < C_N; ++k) {
+    off[k] = total;
+    total += align256(sz[k]);
+  }
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, total, st);
+  if (e != hipSuccess || !ws) {
+    (void)hipGetLastError();
+    return set_error(ETEST_ENOMEM, "cross test workspace of " + std::to_string(total) + " bytes");
+  }
+  char* w = (char*)ws;
+  d.colpart = (double*)(w + off[C_COLPART]);
+  d.colmean = (double*)(w + off[C_COLMEAN]);
+  d.W = w + off[C_W];
+  d.nrm = w + off[C_NRM];
+  d.tsum = (double*)(w + off[C_TSUM]);
+  d.tmax = (float*)(w + off[C_TMAX]);
+  d.rsum = (double*)(w + off[C_V]);
+  d.obs = (double*)(w + off[C_OBS]);
+  d.flags = (int32_t*)(w + off[C_FLAGS]);
+  // launch tables [0, workgroups] of the stages (a one-test batch)
+  const bool f32like = !f64;
+  const int64_t wg[5] = {f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0,
+                         f32like ? (r.p + 63) / 64 : 0, npad / 4, d.ntiles, 0};
+  int64_t hoffs[10];
+  for (int k = 0; k < 5; ++k) {
+    hoffs[2 * k] = 0;
+    hoffs[2 * k + 1] = wg[k];
+  }
+  const TestDesc* D = (const TestDesc*)(w + off[C_DESC]);
+  const int64_t* O = (const int64_t*)(w + off[C_OFFS]);
+  e = hipMemcpyAsync(w + off[C_DESC], &d, sizeof(TestDesc), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + off[C_OFFS], hoffs, sizeof(hoffs), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    // stage timing as for the permutation tests: 0 staging, 1 blocks, 6 statistic
+    const StageEvents* ev = profile_events();
+    auto mark = [&](int k, bool begin) {
+      if (ev && (ev->mask >> k & 1u)) (void)hipEventRecord(begin ? ev->begin[k] : ev->end[k], st);
+    };
+    launch_clear_flags(st, D, nullptr, 1);
+    mark(0, true);
+    launch_colpart(wg[0], st, D, O, 1);
+    launch_colmean(wg[1], st, D, O + 2, 1);
+    launch_stage(wg[2], st, D, O + 4, 1);
+    mark(0, false);
+    mark(1, true);
+    launch_gram(f64 ? PREC_F64 : (r.prec == ETEST_PREC_F32 ? PREC_F32 : PREC_BF16R), wg[3], st, D,
+                O + 6, 1, false);
+    mark(1, false);
+    mark(6, true);
+    launch_cross_final(st, D);
+    mark(6, false);
+    e = hipGetLastError();
+  }
+  // obs[0..3] and flags[0..1] back to the host
+  struct Back { double obs[4]; int32_t flags[2]; };
+  static thread_local Back* hb = nullptr;
+  if (!hb && hipHostMalloc((void**)&hb, sizeof(Back), hipHostMallocDefault) != hipSuccess) hb = nullptr;
+  if (e == hipSuccess && hb) e = hipMemcpyAsync(hb->obs, d.obs, 4 * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && hb) e = hipMemcpyAsync(hb->flags, d.flags, 2 * 4, hipMemcpyDeviceToHost, st);
+  (void)hipFreeAsync(ws, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (!hb) return set_error(ETEST_ENOMEM, "pinned result buffer");
+  if (e != hipSuccess) return set_error(ETEST_EDEVICE, std::string("cross: ") + hipGetErrorString(e));
+  profile_collect();
+  if (hb->flags[0]) return set_error(ETEST_ENONFINITE, "X or Y contains NaN or Inf");
+  out->statistic = hb->obs[0];
+  out->sigma = hb->obs[1];
+  out->z = hb->obs[2];
+  out->p_value = hb->obs[3];
+  out->n_refined = hb->flags[1];
+  return ETEST_OK;
+}

@@ -15,6 +15,7 @@ void launch_clear_flags(hipStream_t st, const TestDesc* d, const int64_t* offs, 
 void launch_colpart(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_colmean(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_stage(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_cross_final(hipStream_t st, const TestDesc* d);
 void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
                  int n, bool dual = false);
 void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);

@@ -22,6 +22,7 @@ void launch_member_public(int64_t, int64_t, uint64_t, int64_t, int64_t, uint32_t
 void launch_member_import(int64_t, hipStream_t, const TestDesc*, const uint32_t*) {}
 void launch_perm(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int, const int32_t*) {}
 void launch_pstat(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_cross_final(hipStream_t, const TestDesc*) {}
 void launch_unpack(bool, int64_t, hipStream_t, const TestDesc*, void*, void*, void*) {}
 }  // namespace et
 
