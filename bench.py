@@ -411,6 +411,27 @@ def run_cross(args):
     return line
 
 
+def run_studies(args):
+    """Section 5.2 studies through the batched path: null p-values and power of the
+    efficient permutation ED test vs the cross-ED test (200 permutations), with the
+    paper's replication counts unless --reps scales them."""
+    from paper_2406_06488_amd import studies
+    scale = args.reps_scale
+    t0 = time.perf_counter()
+    null = studies.null_study(reps=max(1, int(2000 * scale)))
+    power = {name: studies.power_study(st, reps=max(1, int(500 * scale)))
+             for name, st in (("setting_1", studies.SETTING_1), ("setting_2", studies.SETTING_2),
+                              ("setting_3", studies.SETTING_3))}
+    elapsed = time.perf_counter() - t0
+    tests = sum(2 * r["reps"] for r in null) + sum(2 * pt["reps"] for pts in power.values() for pt in pts)
+    line = base_line(args, "studies_section5_2", tests / elapsed, elapsed, 1, "f32",
+                     {"B": 200, "tests": tests})
+    line.update({"metric": "tests/s over the Section 5.2 studies (both tests counted)",
+                 "unit": "tests/s", "null": null, "power": power, "roofline": None,
+                 "cpu_baseline": None})
+    return line
+
+
 def run_serving(args):
     import numpy as np
     import torch
@@ -506,9 +527,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps-scale", type=float, default=1.0,
+                    help="studies: fraction of the paper's replication counts")
     ap.add_argument("--workload", default="plain_f32",
                     choices=["plain_f32", "small_f64", "precision_bf16", "batched", "serving",
-                             "cross_f32", "cross_bf16"])
+                             "cross_f32", "cross_bf16", "studies"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=200.0)
@@ -533,6 +556,8 @@ def main():
         line = run_batched(args)
     elif args.workload.startswith("cross"):
         line = run_cross(args)
+    elif args.workload == "studies":
+        line = run_studies(args)
     else:
         line = run_serving(args)
     print(json.dumps(line), flush=True)
