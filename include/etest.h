@@ -154,6 +154,28 @@ typedef struct {
    EINVAL (arguments), ENONFINITE (NaN / Inf input; out untouched), ENOMEM, EDEVICE. */
 etest_status etest_cross(const etest_request* req, void* stream, etest_cross_result* out);
 
+/* ---- Baselines: the standard and the pre-computation permutation tests ----
+   Same request, splits (split b from (seed, b)), counting rule and result fields as
+   etest_run, so that the three tests can be compared split by split; perm_stats is a device
+   array of B doubles or NULL.  statistic and threshold are both the identity split as
+   evaluated by the baseline's own code.  Synchronous on `stream`.  Errors: EINVAL
+   (arguments), ENONFINITE (NaN / Inf input; perm_stats untouched), ENOMEM, EDEVICE. */
+
+/* Standard permutation test (Alg. 4): for each of the B drawn splits and the identity
+   split, X* and Y* are staged from the pooled rows in index order (x* items first) and the
+   three blocks and the statistic, eq. (1) or (2), are recomputed from them.  The B + 1
+   recomputations run as batched passes of up to 256 tests (each pass one launch per stage,
+   within a 4 GiB workspace).  Cost: (B + 1) times the blocks of one test. */
+etest_status etest_standard(const etest_request* req, void* stream, etest_result* out);
+
+/* Pre-computation permutation test (Alg. 5): the distance (kernel) matrix of the pooled
+   sample, D_WW, is computed once (as the stored upper tiles of the pooled tile grid: each
+   unordered pair once), then for each split the sums of D_WW over x* x x*, y* x y* and
+   x* x y* are taken entry by entry (each entry selected by the split's bits, FP64 sums) and
+   combined into eq. (1) or (2).  Stage timing (etest_profile_enable): 0 staging, 1 blocks,
+   2 split stream, 5 per-split sums, 6 statistics and p-value. */
+etest_status etest_precomputed(const etest_request* req, void* stream, etest_result* out);
+
 /* n independent tests in one batched pass: every stage is one launch covering all tests,
    and the launch sequence is captured once into a HIP graph and replayed while the same
    request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,

@@ -54,6 +54,8 @@ SIGNATURES = [
                              ctypes.POINTER(Result)]),
     ("etest_run", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
     ("etest_cross", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(CrossResult)]),
+    ("etest_standard", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
+    ("etest_precomputed", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
     ("ed_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("mmd_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("etest_batch", c_i32, [ctypes.POINTER(Request), c_i64, c_vp, ctypes.POINTER(Result)]),

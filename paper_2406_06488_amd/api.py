@@ -111,6 +111,32 @@ def run(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True):
     return out
 
 
+def _baseline(fn, X, Y, B, seed, kind, prec, gamma, with_perm_stats):
+    import torch
+    _check_dev(X, Y, prec)
+    ps = torch.empty(max(B, 1), dtype=torch.float64, device=X.device) if with_perm_stats else None
+    req = make_request(X, Y, B, seed, kind, prec, gamma, ps)
+    r = Result()
+    check(getattr(_lib.load(), fn)(ctypes.byref(req), _stream(), ctypes.byref(r)))
+    out = r.as_dict()
+    out["perm_stats"] = ps[:B] if ps is not None else None
+    return out
+
+
+def standard(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True):
+    """Standard permutation test (Alg. 4) on device tensors, synchronous: every split's
+    statistic recomputed from blocks of its own X*, Y*.  Same splits and result fields as
+    run(); statistic and threshold are both the identity split's recomputed statistic."""
+    return _baseline("etest_standard", X, Y, B, seed, kind, prec, gamma, with_perm_stats)
+
+
+def precomputed(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True):
+    """Pre-computation permutation test (Alg. 5) on device tensors, synchronous: the pooled
+    distance (kernel) matrix once, then per split the sums of the entries its index sets
+    select.  Same splits and result fields as run()."""
+    return _baseline("etest_precomputed", X, Y, B, seed, kind, prec, gamma, with_perm_stats)
+
+
 def cross(X, Y, kind="ed", prec="f32", gamma=0.0):
     """Cross-ED / cross-MMD test (permutation-free) on device tensors, synchronous.
     Returns dict(statistic, sigma, z, p_value, n_refined)."""

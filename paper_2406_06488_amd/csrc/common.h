@@ -35,6 +35,8 @@ constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
 constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
 constexpr int FLAG_COUNT = 4;        // int32 index of the 64-bit (count, finished WGs) word
 constexpr int FLAG_WORDS = 8;
+constexpr int PC_ROWS = 32;          // pre-computation test: tile rows per strip
+constexpr int PC_STRIPS = TILE / PC_ROWS;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
 enum { KIND_ED = 0, KIND_MMD = 1 };
@@ -97,15 +99,22 @@ struct TestDesc {
   // rectangle of tiles x side by y side is computed, and each tile keeps its row sums over
   // the x2 columns and over the y2 columns apart.
   int32_t cross, cnx1, cny1, cnx2;
+  // Standard permutation test: staging position t reads pooled item rowmap[t] (x* items in
+  // increasing order, then y* items), so one split's X* and Y* are staged without copying
+  // the data; NULL reads the items in their own order.
+  const int32_t* rowmap;
 };
 
-// Input row t of the pooled sample, in staging order: x rows then y rows; for a cross
-// test x1, y1, x2, y2.
+// Input row t of the pooled sample, in staging order: x rows then y rows (through the
+// row map when there is one); for a cross test x1, y1, x2, y2.
 template <typename T>
 __device__ inline const T* pooled_row(const TestDesc& d, int64_t t) {
   const T* X = (const T*)d.X;
   const T* Y = (const T*)d.Y;
-  if (!d.cross) return t < d.nx ? X + t * d.p : Y + (t - d.nx) * d.p;
+  if (!d.cross) {
+    if (d.rowmap) t = d.rowmap[t];
+    return t < d.nx ? X + t * d.p : Y + (t - d.nx) * d.p;
+  }
   if (t < d.cnx1) return X + t * d.p;
   t -= d.cnx1;
   if (t < d.cny1) return Y + t * d.p;

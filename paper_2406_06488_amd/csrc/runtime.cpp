@@ -100,7 +100,7 @@ static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
   }
 }
 
-TestPlan make_plan(const etest_request& r, int64_t kc_override) {
+TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   TestPlan P;
   TestDesc& d = P.d;
   d.kind = r.kind;
@@ -162,6 +162,16 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   sz[B_FLAGS] = FLAG_WORDS * 4;
   sz[B_RESULT] = sizeof(DevResult);
   sz[B_PERMOUT] = 0;  // set by build_batch when an internal output is needed
+  if (mode != PLAN_EFFICIENT) {  // no centred planes or resampling buffers
+    sz[B_PLANES] = 0;
+    sz[B_PART] = 0;
+    sz[B_PSTAT] = 0;
+    if (mode == PLAN_BLOCKS) sz[B_Z] = 0;
+    if (mode == PLAN_PRECOMP) {
+      sz[B_PART] = (size_t)d.ntiles * PC_STRIPS * 3 * d.B_pad * 8;
+      sz[B_PSTAT] = (size_t)d.B_pad * 8;
+    }
+  }
   size_t o = 0;
   for (int k = 0; k < B_PERMOUT; ++k) {
     P.off[k] = o;
@@ -187,6 +197,11 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override) {
   P.wg[S_PERM_S2] = d.pfmt == PLANES_F16_F16 ? perm_wg : 0;
   P.wg[S_PERM_S3] = d.pfmt == PLANES_F16_E4M3 ? perm_wg : 0;
   P.wg[S_PSTAT] = d.B_pad / 64;
+  if (mode != PLAN_EFFICIENT)
+    for (int k : {S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S2, S_PERM_S3, S_PSTAT})
+      P.wg[k] = 0;
+  if (mode == PLAN_BLOCKS) P.wg[S_MEMBER] = 0;
+  if (mode == PLAN_PRECOMP) P.wg[S_ROWSUM] = 0;
   return P;
 }
 
@@ -1050,3 +1065,157 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
   out->n_refined = hb->flags[1];
   return ETEST_OK;
 }
+
+// ------------------------------------------------- baselines: standard and pre-computation
+namespace et {
+
+// Staging, blocks, block sums and observed statistic of the first m tests of a batch (the
+// launch tables of a prefix of the tests are prefixes of the batch's tables).
+static void enqueue_blocks(const Batch& b, int m, hipStream_t st) {
+  const int n = (int)b.plans.size();
+  auto offs = [&](Slot s) { return b.d_offs + (size_t)s * (n + 1); };
+  auto total = [&](Slot s) { return b.offs[(size_t)s * (n + 1) + m]; };
+  const TestDesc* D = b.d_descs;
+  launch_clear_flags(st, D, nullptr, m);
+  launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), m);
+  launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), m);
+  launch_stage(total(S_STAGE), st, D, offs(S_STAGE), m);
+  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), m, false);
+  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), m, false);
+  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), m, false);
+  launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), m);
+  launch_observed(st, D, nullptr, m);
+}
+
+// Device result -> host, free the workspaces, wait.
+static etest_status finish_baseline(DevResult* d_res, Batch* b, void* aux, hipStream_t st,
+                                    hipError_t e, const char* what, etest_result* out) {
+  DevResult* h = pinned_results(1);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess && h) e = hipMemcpyAsync(h, d_res, sizeof(DevResult), hipMemcpyDeviceToHost, st);
+  free_batch(b, st, true);
+  if (aux) (void)hipFreeAsync(aux, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (!h) return set_error(ETEST_ENOMEM, "pinned result buffer");
+  if (e != hipSuccess) return set_error(ETEST_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return dev_to_result(*h, out);
+}
+
+// Standard test: the B + 1 splits (drawn splits 0..B-1, identity B) are recomputed in
+// passes of up to 256 tests that share one batch workspace; each test stages its split's
+// X*, Y* through a row map and runs staging, Gram, block sums and the observed statistic.
+static etest_status run_standard(const etest_request& r, hipStream_t st, etest_result* out) {
+  init_pool_once();
+  const int64_t n = r.nx + r.ny, W = (n + 31) / 32, B = r.B;
+  etest_request q = r;
+  q.B = 0;
+  q.perm_stats = nullptr;
+  const TestPlan P0 = make_plan(q, 0, PLAN_BLOCKS);
+  const int64_t budget = 4LL << 30;
+  const int64_t chunk =
+      std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(B + 1, 256),
+                                             budget / std::max<int64_t>(1, (int64_t)P0.bytes)));
+  size_t aoff[5], asz[5] = {(size_t)(chunk * n * 4), (size_t)(chunk * W * 4),
+                            (size_t)((B + 1) * 8), (size_t)(FLAG_WORDS * 4), sizeof(DevResult)};
+  size_t atotal = 0;
+  for (int k = 0; k < 5; ++k) {
+    aoff[k] = atotal;
+    atotal += align256(asz[k]);
+  }
+  void* aux = nullptr;
+  hipError_t e = hipMallocAsync(&aux, atotal, st);
+  if (e != hipSuccess || !aux) {
+    (void)hipGetLastError();
+    return set_error(ETEST_ENOMEM, "standard test buffers of " + std::to_string(atotal) + " bytes");
+  }
+  char* a = (char*)aux;
+  int32_t* rowmaps = (int32_t*)(a + aoff[0]);
+  uint32_t* words = (uint32_t*)(a + aoff[1]);
+  double* stats = (double*)(a + aoff[2]);
+  int32_t* flags = (int32_t*)(a + aoff[3]);
+  DevResult* d_res = (DevResult*)(a + aoff[4]);
+  Batch b;
+  b.plans.assign((size_t)chunk, P0);
+  for (int64_t k = 0; k < chunk; ++k) b.plans[(size_t)k].d.rowmap = rowmaps + k * n;
+  etest_status s = place_batch(&b, st, true);
+  if (s != ETEST_OK) {
+    (void)hipFreeAsync(aux, st);
+    return s;
+  }
+  e = hipMemsetAsync(flags, 0, FLAG_WORDS * 4, st);
+  for (int64_t c0 = 0; e == hipSuccess && c0 <= B; c0 += chunk) {
+    const int m = (int)std::min<int64_t>(chunk, B + 1 - c0);
+    const int64_t drawn = std::max<int64_t>(0, std::min<int64_t>(m, B - c0));
+    launch_member_public(r.nx, r.ny, r.seed, c0, drawn, words, st);
+    launch_rowmap(words, drawn, m, n, r.nx, rowmaps, st);
+    enqueue_blocks(b, m, st);
+    launch_collect(b.d_descs, m, c0, B, stats, flags, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) launch_count(stats, B, flags, r.perm_stats, d_res, st);
+  return finish_baseline(d_res, &b, aux, st, e, "standard test", out);
+}
+
+// Pre-computation test: the pooled Gram (D_WW, upper tiles), the split stream, then the
+// per-split class sums of every stored entry and the statistics.
+// Stage timing (etest_profile_enable): 0 staging, 1 blocks, 2 split stream, 5 class sums,
+// 6 statistics + p-value.
+static etest_status run_precomputed(const etest_request& r, hipStream_t st, etest_result* out) {
+  init_pool_once();
+  Batch b;
+  b.plans.push_back(make_plan(r, 0, PLAN_PRECOMP));
+  etest_status s = place_batch(&b, st, true);
+  if (s != ETEST_OK) return s;
+  const TestDesc& d = b.descs[0];
+  const TestDesc* D = b.d_descs;
+  auto offs = [&](Slot k) { return b.d_offs + (size_t)k * 2; };
+  auto total = [&](Slot k) { return b.offs[(size_t)k * 2 + 1]; };
+  const StageEvents* ev = profile_events();
+  auto mark = [&](int k, bool begin) {
+    if (ev && (ev->mask >> k & 1u)) (void)hipEventRecord(begin ? ev->begin[k] : ev->end[k], st);
+  };
+  launch_clear_flags(st, D, nullptr, 1);
+  mark(0, true);
+  launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), 1);
+  launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), 1);
+  launch_stage(total(S_STAGE), st, D, offs(S_STAGE), 1);
+  mark(0, false);
+  mark(2, true);
+  launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), 1);
+  mark(2, false);
+  mark(1, true);
+  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), 1, false);
+  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), 1, false);
+  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 1, false);
+  mark(1, false);
+  mark(5, true);
+  launch_precomp(r.prec == ETEST_PREC_F64, D, d.ntiles, r.B, d.part, st);
+  mark(5, false);
+  mark(6, true);
+  launch_precomp_stat(D, d.ntiles, r.B, d.part, d.pstat, st);
+  launch_count(d.pstat, r.B, d.flags, r.perm_stats, b.d_results, st);
+  mark(6, false);
+  etest_status rs = finish_baseline(b.d_results, &b, nullptr, st, hipSuccess, "pre-computation test", out);
+  profile_collect();
+  return rs;
+}
+
+}  // namespace et
+
+extern "C" {
+
+etest_status etest_standard(const etest_request* req, void* stream, etest_result* out) {
+  if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
+  etest_status s = validate_request(*req);
+  if (s != ETEST_OK) return s;
+  return run_standard(*req, (hipStream_t)stream, out);
+}
+
+etest_status etest_precomputed(const etest_request* req, void* stream, etest_result* out) {
+  if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
+  etest_status s = validate_request(*req);
+  if (s != ETEST_OK) return s;
+  return run_precomputed(*req, (hipStream_t)stream, out);
+}
+
+}  // extern "C"

@@ -29,6 +29,16 @@ void launch_member_import(int64_t bpad, hipStream_t st, const TestDesc* d, const
 void launch_perm(int variant, int64_t blocks, hipStream_t st, const TestDesc* d,
                  const int64_t* offs, int ntests, const int32_t* pcr);
 void launch_pstat(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+void launch_rowmap(const uint32_t* words, int64_t count, int64_t maps, int64_t n, int64_t nx,
+                   int32_t* rowmap, hipStream_t st);
+void launch_collect(const TestDesc* d, int m, int64_t c0, int64_t B, double* stats,
+                    int32_t* flags, hipStream_t st);
+void launch_count(const double* stats, int64_t B, const int32_t* flags, double* perm_out,
+                  DevResult* result, hipStream_t st);
+void launch_precomp(bool f64, const TestDesc* d, int64_t ntiles, int64_t B, double* part,
+                    hipStream_t st);
+void launch_precomp_stat(const TestDesc* d, int64_t ntiles, int64_t B, const double* part,
+                         double* stats, hipStream_t st);
 void launch_unpack(bool f64, int64_t elems, hipStream_t st, const TestDesc* d, void* xx, void* yy,
                    void* xy);
 
@@ -62,7 +72,10 @@ struct TestPlan {
 // Sets the calling thread's error message; returns the status.
 etest_status set_error(etest_status s, const std::string& msg);
 etest_status validate_request(const etest_request& r);
-TestPlan make_plan(const etest_request& r, int64_t kc_override = 0);
+// Plan modes: the efficient test; blocks and observed statistic only (one recomputation of
+// the standard test); pooled blocks, split stream and the pre-computation test's buffers.
+enum PlanMode { PLAN_EFFICIENT = 0, PLAN_BLOCKS = 1, PLAN_PRECOMP = 2 };
+TestPlan make_plan(const etest_request& r, int64_t kc_override = 0, int mode = PLAN_EFFICIENT);
 
 // A set of tests laid out in one device workspace, ready to launch.
 struct Batch {

@@ -24,6 +24,11 @@ void launch_perm(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int
 void launch_pstat(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_cross_final(hipStream_t, const TestDesc*) {}
 void launch_unpack(bool, int64_t, hipStream_t, const TestDesc*, void*, void*, void*) {}
+void launch_rowmap(const uint32_t*, int64_t, int64_t, int64_t, int64_t, int32_t*, hipStream_t) {}
+void launch_collect(const TestDesc*, int, int64_t, int64_t, double*, int32_t*, hipStream_t) {}
+void launch_count(const double*, int64_t, const int32_t*, double*, DevResult*, hipStream_t) {}
+void launch_precomp(bool, const TestDesc*, int64_t, int64_t, double*, hipStream_t) {}
+void launch_precomp_stat(const TestDesc*, int64_t, int64_t, const double*, double*, hipStream_t) {}
 }  // namespace et
 
 using namespace et;
@@ -87,6 +92,45 @@ static void check_plan(const etest_request& r, bool internal) {
         "part outside");
 }
 
+// Plans of the two baselines: blocks only (one recomputation of the standard test) and the
+// pre-computation test (pooled blocks, split stream, strip sums, split statistics).
+static void check_mode_plan(const etest_request& r, int mode) {
+  const TestPlan P = make_plan(r, 0, mode);
+  const TestDesc& d0 = P.d;
+  const int64_t npad = (int64_t)d0.nt * TILE;
+  const bool f64 = r.prec == ETEST_PREC_F64;
+  size_t need[B_NBUF] = {};
+  need[B_W] = (size_t)npad * d0.p_pad * (f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2));
+  need[B_D] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 4);
+  need[B_RSUM] = (size_t)npad * 16;
+  need[B_TSUM] = (size_t)d0.ntiles * 2 * TILE * 8;
+  if (mode == PLAN_PRECOMP) {
+    // k_precomp reads Z columns below ceil((B + 1) / 64) * 64 and writes strip sums of the
+    // columns up to B; k_precomp_stat writes B + 1 statistics
+    const int64_t cols = (r.B + 1 + 63) / 64 * 64;
+    CHECK(cols <= d0.B_pad, "precomp columns %lld > B_pad %lld", (long long)cols,
+          (long long)d0.B_pad);
+    need[B_Z] = (size_t)d0.nt * TILE_WORDS * d0.B_pad * 4;
+    need[B_PART] = (size_t)d0.ntiles * PC_STRIPS * 3 * d0.B_pad * 8;
+    need[B_PSTAT] = (size_t)(r.B + 1) * 8;
+  }
+  for (int k = 0; k < B_PERMOUT; ++k) {
+    CHECK(P.size[k] >= need[k], "mode %d buffer %d: %zu < %zu", mode, k, P.size[k], need[k]);
+    CHECK(P.off[k] + P.size[k] <= P.bytes, "mode %d buffer %d past the region", mode, k);
+    for (int m = 0; m < k; ++m) {
+      if (P.size[k] == 0 || P.size[m] == 0) continue;
+      const bool apart = P.off[k] + P.size[k] <= P.off[m] || P.off[m] + P.size[m] <= P.off[k];
+      CHECK(apart, "mode %d buffers %d and %d overlap", mode, k, m);
+    }
+  }
+  CHECK(P.size[B_PLANES] == 0, "mode %d keeps centred planes", mode);
+  for (int k : {S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S2, S_PERM_S3, S_PSTAT})
+    CHECK(P.wg[k] == 0, "mode %d launches slot %d", mode, k);
+  CHECK((P.wg[S_MEMBER] > 0) == (mode == PLAN_PRECOMP), "mode %d split stream", mode);
+  CHECK(P.bytes < make_plan(r).bytes || r.B == 0 || mode == PLAN_PRECOMP,
+        "blocks-only plan not smaller than the full plan");
+}
+
 // Row units of the resampling stage: rowk_coords against a plain enumeration (row by row,
 // kc tiles at a time); together the units cover every stored tile (i <= j) exactly once.
 static void check_row_units() {
@@ -135,6 +179,10 @@ int main() {
             r.Y = (const void*)0x2000;
             r.perm_stats = with_out ? (double*)0x3000 : nullptr;
             check_plan(r, internal != 0);
+            if (!internal && !with_out) {
+              check_mode_plan(r, PLAN_BLOCKS);
+              check_mode_plan(r, PLAN_PRECOMP);
+            }
           }
   std::printf("%s (%d failures)\n", failures ? "FAILED" : "ok", failures);
   return failures ? 1 : 0;

@@ -1,0 +1,137 @@
+"""The standard (Alg. 4) and pre-computation (Alg. 5) permutation tests on the GPU, through
+the C ABI, against the FP64 oracle and against the efficient path on the same splits.
+
+All three tests evaluate the same statistic on the same splits (the efficient test's
+defining property), so each baseline's per-split statistics are held to the oracle with the
+efficient path's tolerances (FP64 1e-12, FP32 1e-5, BF16-refined 1e-3 on the null-mean
+scale), and in FP64 to the efficient path itself."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_06488_amd import _lib, api, inputs
+from tests.gpu_helpers import BF16_MIN_P, bf16_exact_pair, compare_run, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+KIND = {"ed": oracle.ED, "mmd": oracle.MMD}
+METHODS = {"standard": api.standard, "precomputed": api.precomputed}
+
+
+def _dev(a, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dt)
+
+
+def _data(nx, ny, p, seed, prec, shift=0.1):
+    dt = np.float64 if prec == "f64" else np.float32
+    X, Y = inputs.gaussian_pair(nx, ny, p, seed, mean_shift=shift, dtype=dt)
+    if prec == "bf16r" and p < BF16_MIN_P:
+        X, Y = bf16_exact_pair(X, Y)
+    return X, Y
+
+
+CASES = [
+    # nx, ny, p, B, data seed, perm seed, shift
+    (100, 100, 10, 400, 0, 1, 0.0),
+    (300, 170, 37, 300, 3, 5, 0.15),     # several tiles, ragged tails; standard: 2 passes
+    (129, 127, 64, 255, 4, 6, 0.3),      # one row past a tile / one short
+    (1, 5, 3, 40, 5, 7, 0.5),
+    (7, 1, 2, 40, 6, 8, 0.5),
+    (1, 1, 4, 20, 7, 9, 1.0),            # only two distinct splits: exact ties
+    (40, 33, 1, 300, 8, 10, 0.2),        # p = 1
+    (200, 160, 1030, 100, 9, 11, 0.1),   # FP32 Gram split over K
+]
+
+
+@pytest.mark.parametrize("method", ["standard", "precomputed"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_baseline_matches_oracle(case, kind, prec, method):
+    nx, ny, p, B, ds, ps_, shift = CASES[case]
+    say("baseline", method, case, kind, prec, nx, ny, p, B)
+    X, Y = _data(nx, ny, p, ds, prec, shift)
+    gamma = 1.0 / p
+    g = METHODS[method](_dev(X, prec), _dev(Y, prec), B, ps_, kind, prec, gamma)
+    torch.cuda.synchronize()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, ps_, KIND[kind], gamma)
+    near = compare_run(g, o, prec, "%s case %d %s %s" % (method, case, kind, prec))
+    if len(near):
+        say("near-ties within tolerance:", near.tolist())
+
+
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+def test_three_tests_agree_split_by_split(kind):
+    """FP64: the efficient, pre-computation and standard tests give the same statistic on
+    every split (to rounding) and the same p-value."""
+    nx, ny, p, B = 230, 190, 20, 600   # standard test: three passes of up to 256 tests
+    say("agree", kind, nx, ny, p, B)
+    X, Y = _data(nx, ny, p, 21, "f64", 0.05)
+    Xd, Yd = _dev(X, "f64"), _dev(Y, "f64")
+    gamma = 1.0 / p
+    e = api.run(Xd, Yd, B, 77, kind, "f64", gamma)
+    pc = api.precomputed(Xd, Yd, B, 77, kind, "f64", gamma)
+    st = api.standard(Xd, Yd, B, 77, kind, "f64", gamma)
+    torch.cuda.synchronize()
+    ref = e["perm_stats"].cpu().numpy()
+    scale = max(float(np.mean(np.abs(ref))), abs(e["statistic"]))
+    for name, r in (("precomputed", pc), ("standard", st)):
+        v = r["perm_stats"].cpu().numpy()
+        assert np.abs(v - ref).max() <= 1e-12 * scale, (name, np.abs(v - ref).max(), scale)
+        assert abs(r["statistic"] - e["statistic"]) <= 1e-12 * scale, name
+        assert r["count_ge"] == e["count_ge"] and r["p_value"] == e["p_value"], name
+
+
+@pytest.mark.parametrize("method", ["standard", "precomputed"])
+def test_zero_and_one_permutations(method):
+    X, Y = _data(20, 30, 5, 1, "f32")
+    g = METHODS[method](_dev(X, "f32"), _dev(Y, "f32"), 0, 1, "ed", "f32")
+    assert g["p_value"] == 1.0 and g["count_ge"] == 0 and g["B"] == 0
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), 1, 1)
+    g = METHODS[method](_dev(X, "f32"), _dev(Y, "f32"), 1, 1, "ed", "f32")
+    compare_run(g, o, "f32")
+
+
+@pytest.mark.parametrize("method", ["etest_standard", "etest_precomputed"])
+def test_nonfinite_input_rejected_and_outputs_untouched(method):
+    X, Y = _data(50, 40, 6, 2, "f32")
+    Y[7, 1] = np.inf
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    ps = torch.full((100,), 7.0, dtype=torch.float64, device=DEV)
+    req = api.make_request(Xd, Yd, 100, 1, "ed", "f32", 0.0, ps)
+    r = _lib.Result()
+    st = getattr(_lib.load(), method)(ctypes.byref(req), None, ctypes.byref(r))
+    assert st == _lib.ENONFINITE
+    assert torch.all(ps == 7.0)
+
+
+@pytest.mark.parametrize("method", ["etest_standard", "etest_precomputed"])
+def test_bad_arguments_rejected(method):
+    fn = getattr(_lib.load(), method)
+    X, Y = _data(10, 10, 3, 2, "f32")
+    req = api.make_request(_dev(X, "f32"), _dev(Y, "f32"), 10, 1, "ed", "f32", 0.0, None)
+    r = _lib.Result()
+    assert fn(None, None, ctypes.byref(r)) == _lib.EINVAL
+    assert fn(ctypes.byref(req), None, None) == _lib.EINVAL
+    req.nx = 0
+    assert fn(ctypes.byref(req), None, ctypes.byref(r)) == _lib.EINVAL
+
+
+@pytest.mark.parametrize("nx,p", [(1000, 500), (200, 2000)])
+def test_paper_timing_shapes(nx, p):
+    """The largest shapes of the paper's two timing experiments (B = 200), FP32 form:
+    both baselines against the oracle split by split."""
+    B = 200
+    say("timing shape", nx, p, B)
+    X, Y = _data(nx, nx, p, 31, "f32", 0.0)
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, 3)
+    for name, fn in METHODS.items():
+        g = fn(Xd, Yd, B, 3, "ed", "f32")
+        torch.cuda.synchronize()
+        compare_run(g, o, "f32", "%s %d %d" % (name, nx, p))
