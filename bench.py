@@ -18,6 +18,10 @@ Workloads (--workload):
                   run one by one are timed beside it
   serving         Poisson stream of tests (200/s by default) through the continuous-batching
                   server; latency p50 / p99 and served tests per second
+  cross_f32/_bf16 cross-ED test (permutation-free) on the plain_f32 / precision_bf16 data
+  studies         Section 5.2 null and power studies (efficient test vs cross-ED)
+  timing          Section 5.1 computing-time experiments: standard, pre-computation,
+                  efficient and cross-ED tests, B = 200, FP64 and FP32 forms
 
 Prints ONE JSON line on stdout.  Per-stage device times come from HIP events recorded by
 the library on the launch stream.
@@ -432,6 +436,110 @@ def run_studies(args):
     return line
 
 
+# VALU issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+PRECOMP_OPS_PER_ENTRY = 3   # two ANDs (select) and one FP64 add per entry and split
+
+
+def run_timing(args):
+    """Section 5.1 computing-time experiments on one GPU: seconds per test of the standard
+    (Alg. 4), pre-computation (Alg. 5), efficient (Alg. 1) and cross-ED (Alg. 7) energy
+    distance tests with B = 200, data N_p(0, I); experiment 1: p = 500, nx = ny = 100..1000;
+    experiment 2: nx = ny = 200, p = 200..2000.  Wall time of each synchronous call (inputs
+    already on the device), averaged over --timing-reps replications (half as many for the
+    standard test, as in the paper's ratio of 10 to 100), each on freshly drawn data."""
+    import numpy as np
+    import torch
+
+    from paper_2406_06488_amd import api
+    B = 200
+    exps = {"exp1_p500_n": [(n, 500) for n in range(100, 1001, 100)],
+            "exp2_n200_p": [(200, p) for p in range(200, 2001, 200)]}
+    precs = [q for q in args.timing_precs.split(",") if q]
+    fns = {
+        "standard": lambda X, Y, q: api.standard(X, Y, B, 1, "ed", q, with_perm_stats=False),
+        "precomputed": lambda X, Y, q: api.precomputed(X, Y, B, 1, "ed", q,
+                                                       with_perm_stats=False),
+        "efficient": lambda X, Y, q: api.run(X, Y, B, 1, "ed", q, with_perm_stats=False),
+        "cross": lambda X, Y, q: api.cross(X, Y, "ed", q),
+    }
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(20240610)
+    tables = {}
+    t_all = time.perf_counter()
+    for q in precs:
+        dt = torch.float64 if q == "f64" else torch.float32
+        for ename, shapes in exps.items():
+            tab = {}
+            for n, p in shapes:
+                key = str(n if ename.startswith("exp1") else p)
+                row = {}
+                for mname, fn in fns.items():
+                    reps = args.timing_reps if mname != "standard" else max(1, args.timing_reps // 2)
+                    X = torch.randn(n, p, generator=gen, device="cuda", dtype=dt)
+                    Y = torch.randn(n, p, generator=gen, device="cuda", dtype=dt)
+                    fn(X, Y, q)  # first call of the shape: pools and modules warm
+                    ts = []
+                    for _ in range(reps):
+                        X = torch.randn(n, p, generator=gen, device="cuda", dtype=dt)
+                        Y = torch.randn(n, p, generator=gen, device="cuda", dtype=dt)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        fn(X, Y, q)
+                        ts.append(time.perf_counter() - t0)
+                    row[mname] = {"mean_ms": 1e3 * float(np.mean(ts)),
+                                  "min_ms": 1e3 * float(np.min(ts)), "reps": reps}
+                row["speedup_vs_standard"] = row["standard"]["mean_ms"] / row["efficient"]["mean_ms"]
+                row["speedup_vs_precomputed"] = (row["precomputed"]["mean_ms"] /
+                                                 row["efficient"]["mean_ms"])
+                tab[key] = row
+                log(q, ename, key, {m: round(row[m]["mean_ms"], 3) for m in fns})
+            tables["%s_%s" % (q, ename)] = tab
+    elapsed = time.perf_counter() - t_all
+    # the per-split sums of the pre-computation test at the largest experiment-1 shape:
+    # kernel time from HIP events on its launch stream, against the VALU issue bound
+    n, p = 1000, 500
+    X = torch.randn(n, p, generator=gen, device="cuda", dtype=torch.float32)
+    Y = torch.randn(n, p, generator=gen, device="cuda", dtype=torch.float32)
+    fns["precomputed"](X, Y, "f32")
+    torch.cuda.synchronize()
+    api.profile_enable(True, ["resampling"])
+    for _ in range(5):
+        fns["precomputed"](X, Y, "f32")
+    prof = per_launch(api.profile_read())
+    api.profile_enable(False)
+    pc_ms = prof["resampling"]
+    entries = (B + 1) * (2 * n) * (2 * n + 1) / 2.0   # every unordered pooled pair, every split
+    achieved = entries / (pc_ms * 1e-3)
+    peak = VALU_LANE_OPS / PRECOMP_OPS_PER_ENTRY
+    big = tables.get("f32_exp1_p500_n", tables[next(iter(tables))])["1000"]
+    line = base_line(args, "timing_section5_1", 1e3 / big["efficient"]["mean_ms"], elapsed, 1,
+                     "f32", {"B": B, "experiments": list(exps), "precisions": precs,
+                             "reps": args.timing_reps})
+    line.update({"metric": "efficient ED tests/s at nx = ny = 1000, p = 500, B = 200 "
+                           "(Section 5.1 timing experiments, all four tests timed)",
+                 "unit": "tests/s", "tables": tables,
+                 "roofline": {"bound": "alu", "kernel": "k_precomp<float>",
+                              "achieved": achieved, "peak": peak,
+                              "unit": "entry selections/s",
+                              "algorithmic": "(B+1) n(n+1)/2 = %.4g per launch" % entries,
+                              "frac": achieved / peak, "traffic": None, "ms": pc_ms}})
+    if not args.no_cpu_baseline:
+        import oracle
+        Xh, Yh = X.double().cpu().numpy(), Y.double().cpu().numpy()
+        log("cpu baseline (oracle) ...")
+        t0 = time.perf_counter()
+        oracle.run_test(Xh, Yh, B, 1)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "tests/s",
+                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+                                "kind": "oracle",
+                                "sample": "one whole test, nx = ny = 1000, p = 500, B = 200"}
+    else:
+        line["cpu_baseline"] = None
+    return line
+
+
 def run_serving(args):
     import numpy as np
     import torch
@@ -531,7 +639,11 @@ def main():
                     help="studies: fraction of the paper's replication counts")
     ap.add_argument("--workload", default="plain_f32",
                     choices=["plain_f32", "small_f64", "precision_bf16", "batched", "serving",
-                             "cross_f32", "cross_bf16", "studies"])
+                             "cross_f32", "cross_bf16", "studies", "timing"])
+    ap.add_argument("--timing-reps", type=int, default=20,
+                    help="timing: replications per shape and test (standard test: half)")
+    ap.add_argument("--timing-precs", default="f64,f32",
+                    help="timing: comma-separated forms to time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=200.0)
@@ -558,6 +670,8 @@ def main():
         line = run_cross(args)
     elif args.workload == "studies":
         line = run_studies(args)
+    elif args.workload == "timing":
+        line = run_timing(args)
     else:
         line = run_serving(args)
     print(json.dumps(line), flush=True)

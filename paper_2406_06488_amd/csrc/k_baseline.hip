@@ -126,15 +126,10 @@ __global__ void __launch_bounds__(1024) k_count(const double* __restrict__ stats
 // Padding entries are 0.  One wave per (tile, 32-row strip, 64 splits): the strip sits in
 // LDS and every lane (one split) reads the same entry, selects it by its own column bit and
 // adds it in FP64.  No matrix product: this is the per-split extraction of Alg. 5.
-// Entry v where the column mask m (0 or all ones, the lane's split bit of that column)
-// is set, else 0: both halves of v's bits ANDed with m.
-__device__ inline double pc_select(double v, uint32_t m) {
-  const uint64_t mm = ((uint64_t)m << 32) | m;
-  return __longlong_as_double((long long)((uint64_t)__double_as_longlong(v) & mm));
-}
-
-// The strip is held in LDS as FP64 (the stored FP32 entries converted once), so that the
-// per-split work is a select and an FP64 add per entry.
+// The strip is held in LDS as FP64 (the stored FP32 entries converted once).  An entry is
+// selected by a fused multiply-add with the lane's column bit as 0.0 or 1.0, which adds it
+// exactly or leaves the sum as it is; the bits, fixed for the whole strip, are converted
+// once, so each entry costs one FMA.
 template <typename T>
 __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ descs,
                                                 double* __restrict__ part, int64_t sg) {
@@ -147,10 +142,20 @@ __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ des
   int i, j;
   tile_coords(t, d.nt, &i, &j);
   const int lane = threadIdx.x;
-  const T* src = (const T*)d.D + (int64_t)t * TILE * TILE + (int64_t)h * PC_ROWS * TILE;
-  for (int e = lane * 2; e < PC_ROWS * TILE; e += 128) {
-    Ds[e] = (double)src[e];
-    Ds[e + 1] = (double)src[e + 1];
+  {  // the 32 x 128 strip: every 16-byte load of the lane in flight before the LDS stores
+    const uint4* src = (const uint4*)((const T*)d.D + (int64_t)t * TILE * TILE +
+                                      (int64_t)h * PC_ROWS * TILE);
+    constexpr int PER = 16 / sizeof(T);                  // entries per load
+    constexpr int NLD = PC_ROWS * TILE / PER / 64;       // loads per lane
+    uint4 v[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) v[k] = src[lane + 64 * k];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const T* e = (const T*)&v[k];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) Ds[(lane + 64 * k) * PER + q] = (double)e[q];
+    }
   }
   __syncthreads();
   {  // row totals of the strip, two lanes per row, fixed order
@@ -161,18 +166,9 @@ __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ des
   }
   __syncthreads();
   const int64_t s = g * 64 + lane;  // < B_pad: Z columns past B hold no members
-  // the lane's column masks, formed once for the whole strip (the empty asm keeps them as
-  // plain words, so that each entry costs two ANDs and one FP64 add)
-  uint32_t colmask[TILE];
+  uint32_t zc[TILE_WORDS];
 #pragma unroll
-  for (int q = 0; q < TILE_WORDS; ++q) {
-    const uint32_t zw = d.Z[(int64_t)(j * TILE_WORDS + q) * d.B_pad + s];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      colmask[q * 32 + k] = (uint32_t)((int32_t)(zw << (31 - k)) >> 31);
-      asm volatile("" : "+v"(colmask[q * 32 + k]));
-    }
-  }
+  for (int q = 0; q < TILE_WORDS; ++q) zc[q] = d.Z[(int64_t)(j * TILE_WORDS + q) * d.B_pad + s];
   const uint32_t zr = d.Z[(int64_t)(i * TILE_WORDS + h) * d.B_pad + s];
   const bool diag = i == j;
   double wxx = 0.0, wyy = 0.0, wxy = 0.0;
@@ -180,7 +176,8 @@ __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ des
     const double* row = Ds + r * TILE;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < TILE; ++c) a[c & 3] += pc_select(row[c], colmask[c]);
+    for (int c = 0; c < TILE; ++c)
+      a[c & 3] = fma(row[c], (double)((zc[c >> 5] >> (c & 31)) & 1u), a[c & 3]);
     const double sx = (a[0] + a[1]) + (a[2] + a[3]);
     const double sy = (half_tot[r][0] + half_tot[r][1]) - sx;
     const bool member = (zr >> r) & 1u;
@@ -217,22 +214,32 @@ struct Csum2 {  // Neumaier-compensated sum
   __device__ double value() const { return s + c; }
 };
 
-// Statistic of split column s (0 <= s <= B) from the strip sums, in strip order.
-__global__ void __launch_bounds__(256) k_precomp_stat(const TestDesc* __restrict__ descs,
-                                                      const double* __restrict__ part,
-                                                      int64_t nstrips, double* __restrict__ stats) {
+// Statistics of 64 split columns per workgroup: 16 groups of waves each take every 16th
+// strip (compensated sums), then wave 0 adds the 16 group sums in order.
+constexpr int PCS_GROUPS = 16;
+__global__ void __launch_bounds__(64 * PCS_GROUPS) k_precomp_stat(const TestDesc* __restrict__ descs,
+                                                                  const double* __restrict__ part,
+                                                                  int64_t nstrips,
+                                                                  double* __restrict__ stats) {
+  __shared__ double red[3][PCS_GROUPS][64];
   const TestDesc d = descs[0];
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s > d.B) return;
-  Csum2 xx, yy, xy;
-  for (int64_t u = 0; u < nstrips; ++u) {
-    xx.add(part[(u * 3 + 0) * d.B_pad + s]);
-    yy.add(part[(u * 3 + 1) * d.B_pad + s]);
-    xy.add(part[(u * 3 + 2) * d.B_pad + s]);
-  }
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t s = (int64_t)blockIdx.x * 64 + c;  // < B_pad
+  Csum2 acc[3];
+  for (int64_t u = g; u < nstrips; u += PCS_GROUPS)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[k].add(part[(u * 3 + k) * d.B_pad + s]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) red[k][g][c] = acc[k].value();
+  __syncthreads();
+  if (g != 0 || s > d.B) return;
+  Csum2 w[3];
+  for (int q = 0; q < PCS_GROUPS; ++q)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k].add(red[k][q][c]);
   const double nx = d.nx, ny = d.ny;
-  const double txx = xx.value() / (nx * nx), tyy = yy.value() / (ny * ny);
-  const double txy = 2.0 * xy.value() / (nx * ny);
+  const double txx = w[0].value() / (nx * nx), tyy = w[1].value() / (ny * ny);
+  const double txy = 2.0 * w[2].value() / (nx * ny);
   stats[s] = d.kind == KIND_ED ? (txy - txx) - tyy : (txx + tyy) - txy;
 }
 
@@ -265,8 +272,8 @@ void launch_precomp(bool f64, const TestDesc* d, int64_t ntiles, int64_t B, doub
 }
 void launch_precomp_stat(const TestDesc* d, int64_t ntiles, int64_t B, const double* part,
                          double* stats, hipStream_t st) {
-  hipLaunchKernelGGL(k_precomp_stat, dim3((unsigned)((B + 1 + 255) / 256)), dim3(256), 0, st, d,
-                     part, ntiles * PC_STRIPS, stats);
+  hipLaunchKernelGGL(k_precomp_stat, dim3((unsigned)((B + 1 + 63) / 64)), dim3(64 * PCS_GROUPS), 0,
+                     st, d, part, ntiles * PC_STRIPS, stats);
 }
 
 }  // namespace et

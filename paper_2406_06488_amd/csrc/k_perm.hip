@@ -253,42 +253,60 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
   }
 }
 
-// FP64: thread = split column; rows of the centred tile are staged 32 at a time.
+// FP64: thread = split column (a workgroup covers 256 columns of a chunk); each workgroup
+// takes one 32-row strip of its row unit's centred tiles (the row units of an FP64 test are
+// PC_STRIPS times as many as its row-unit walk gives: unit rks = row unit rks / PC_STRIPS,
+// strip rks % PC_STRIPS), so that even a test of two tiles spreads over several CUs.
 __global__ void __launch_bounds__(256) k_perm_f64(const TestDesc* __restrict__ descs,
                                                   const int64_t* __restrict__ offs, int ntests,
                                                   const int32_t* __restrict__ pcr) {
-  __shared__ double Ts[32 * TILE];
+  __shared__ double Ts[PC_ROWS * TILE];
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
-  const PermUnit u = perm_unit(d, ti, blockIdx.x - offs[ti], pcr);
+  const int pc0 = pcr ? pcr[2 * ti] : 0;
+  const int pcn = pcr ? pcr[2 * ti + 1] : (int)(d.B_pad / NP);
+  const int ncr = (pcn + d.cc - 1) / d.cc;
+  const int64_t local = blockIdx.x - offs[ti];
+  const int rks = (int)(local / ncr);
+  const int cr = (int)(local % ncr);
+  const int h = rks % PC_STRIPS;
+  int i, j0, j1;
+  rowk_coords(d, rks / PC_STRIPS, &i, &j0, &j1);
+  const int cb = pc0 + cr * d.cc, ce = min(pc0 + pcn, cb + d.cc);
   const int tid = threadIdx.x;
   const uint32_t* Z = d.Z;
-  for (int c = u.cb; c < u.ce; ++c) {
+  constexpr int NLD = PC_ROWS * TILE / 2 / 256;  // 16-byte loads per thread per strip
+  for (int c = cb; c < ce; ++c) {
     const int64_t col = (int64_t)c * NP + tid;
-    uint32_t zi[TILE_WORDS];
-    for (int q = 0; q < TILE_WORDS; ++q) zi[q] = Z[(int64_t)(u.i * TILE_WORDS + q) * d.B_pad + col];
+    const uint32_t zi = Z[(int64_t)(i * TILE_WORDS + h) * d.B_pad + col];
     double acc = 0.0;
-    for (int j = u.j0; j < u.j1; ++j) {
+    for (int j = j0; j < j1; ++j) {
       uint32_t zj[TILE_WORDS];
+#pragma unroll
       for (int q = 0; q < TILE_WORDS; ++q) zj[q] = Z[(int64_t)(j * TILE_WORDS + q) * d.B_pad + col];
-      const double* Tt = (const double*)d.planes + (int64_t)tile_index(u.i, j, d.nt) * TILE * TILE;
-      for (int rc = 0; rc < TILE_WORDS; ++rc) {
-        __syncthreads();
-        for (int e = tid; e < 32 * TILE; e += 256) Ts[e] = Tt[(int64_t)rc * 32 * TILE + e];
-        __syncthreads();
-        for (int rr = 0; rr < 32; ++rr) {
-          double v = 0.0;
-          for (int q = 0; q < TILE_WORDS; ++q) {
-            const uint32_t wq = zj[q];
-#pragma unroll 8
-            for (int b = 0; b < 32; ++b)
-              v = fma(Ts[rr * TILE + q * 32 + b], (double)((wq >> b) & 1u), v);
-          }
-          if ((zi[rc] >> rr) & 1u) acc += v;
+      const double2* Tt = (const double2*)((const double*)d.planes +
+                                           (int64_t)tile_index(i, j, d.nt) * TILE * TILE +
+                                           (int64_t)h * PC_ROWS * TILE);
+      double2 v[NLD];  // every load of the strip in flight before the first LDS store
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) v[k] = Tt[tid + 256 * k];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NLD; ++k) ((double2*)Ts)[tid + 256 * k] = v[k];
+      __syncthreads();
+      for (int rr = 0; rr < PC_ROWS; ++rr) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < TILE_WORDS; ++q) {
+          const uint32_t wq = zj[q];
+#pragma unroll
+          for (int b = 0; b < 32; ++b)
+            a[b & 3] = fma(Ts[rr * TILE + q * 32 + b], (double)((wq >> b) & 1u), a[b & 3]);
         }
+        if ((zi >> rr) & 1u) acc += (a[0] + a[1]) + (a[2] + a[3]);
       }
     }
-    d.part[(int64_t)u.rk * d.B_pad + col] = acc;
+    d.part[(int64_t)rks * d.B_pad + col] = acc;
   }
 }
 

@@ -91,11 +91,14 @@ static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
   const int64_t nt = (r.nx + TILE - 1) / TILE + (r.ny + TILE - 1) / TILE;
   const int64_t chunks = (r.B + 1 + NP - 1) / NP;
   const int64_t ncr = (chunks + *cc - 1) / *cc;
+  // the FP64 kernel runs PC_STRIPS workgroups per row unit and may go down to one tile each
+  const bool f64 = r.prec == ETEST_PREC_F64;
+  const int64_t strips = f64 ? PC_STRIPS : 1;
   *kc = 16;
-  while (*kc > 2) {
+  while (*kc > (f64 ? 1 : 2)) {
     int64_t nrk = 0;
     for (int64_t i = 0; i < nt; ++i) nrk += (nt - i + *kc - 1) / *kc;
-    if (nrk * ncr >= 512) break;
+    if (nrk * strips * ncr >= 512) break;
     *kc /= 2;
   }
 }
@@ -125,7 +128,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   d.kc = (int32_t)(kc_override > 0 ? kc_override : kc_t);
   int nrk = 0;
   for (int i = 0; i < d.nt; ++i) nrk += (d.nt - i + d.kc - 1) / d.kc;
-  d.n_rowk = nrk;
+  d.n_rowk = r.prec == ETEST_PREC_F64 ? nrk * PC_STRIPS : nrk;  // FP64: one unit per strip
   const int64_t n = r.nx + r.ny;
   d.nrowchunks = (int32_t)((n + COLSUM_ROWS - 1) / COLSUM_ROWS);
   d.B = r.B;
