@@ -437,8 +437,9 @@ def run_studies(args):
 
 
 # VALU issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+# (FP64 FMA issues at the full rate: 78.6 TFLOP/s = this rate x 2 flops)
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-PRECOMP_OPS_PER_ENTRY = 3   # two ANDs (select) and one FP64 add per entry and split
+PRECOMP_OPS_PER_ENTRY = 1   # one FP64 FMA (entry x split bit) per entry and split
 
 
 def run_timing(args):
