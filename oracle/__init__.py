@@ -15,6 +15,10 @@ What each function follows (Chaibub Neto, arXiv 2406.06488):
   perm_stat()     the Alg. 1 loop body: permuted blocks filled from the four
                   sub-blocks, then eq. (1)/(2).
   run_test()      Alg. 1 end to end, p-value as in Section 3.1.
+  permutation(), hsic(), hsic_test()
+                  the HSIC independence permutation test of the paper's
+                  discussion (unbiased HSIC of Song et al. 2012; permutations
+                  of the y sample from Philox keys).
 """
 import ctypes
 import os
@@ -56,6 +60,10 @@ def lib():
                                ctypes.c_uint64, dp, dp, dp, i64p, dp, ctypes.c_int]
         L.orc_cross.argtypes = [ctypes.c_int, dp, i64, dp, i64, i64, ctypes.c_double, dp,
                                 ctypes.c_int]
+        L.orc_permutation.argtypes = [i64, ctypes.c_uint64, i64, i64p]
+        L.orc_hsic.argtypes = [dp, dp, i64, i64p, dp]
+        L.orc_hsic_test.argtypes = [dp, dp, i64, i64, i64, ctypes.c_double, ctypes.c_double, i64,
+                                    ctypes.c_uint64, dp, dp, i64p, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -200,3 +208,43 @@ def cross(X, Y, kind=ED, gamma=1.0, nthreads=0):
         raise ValueError("cross: invalid arguments (nx, ny >= 2, p >= 1, gamma > 0 for MMD)")
     return {"statistic": float(out[0]), "sigma": float(out[1]), "z": float(out[2]),
             "p_value": float(out[3])}
+
+
+def permutation(n, seed, b):
+    """Permutation b of 0..n-1 (items ordered by their Philox key, ties by index)."""
+    out = np.empty(n, dtype=np.int64)
+    if lib().orc_permutation(n, seed, b, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))):
+        raise ValueError("permutation: n >= 1, b >= 0")
+    return out
+
+
+def hsic(K, L, perm=None):
+    """Unbiased HSIC of kernel matrices K and L, L read through perm (None: identity)."""
+    K, L = _f64(K), _f64(L)
+    n = K.shape[0]
+    out = ctypes.c_double()
+    pp = None
+    if perm is not None:
+        perm = np.ascontiguousarray(perm, dtype=np.int64)
+        pp = perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    if lib().orc_hsic(_d(K), _d(L), n, pp, ctypes.byref(out)):
+        raise ValueError("hsic: n >= 4")
+    return out.value
+
+
+def hsic_test(X, Y, B, seed, gamma_x, gamma_y, nthreads=0):
+    """HSIC independence permutation test on paired rows of X (n x p) and Y (n x q)."""
+    X, Y = _f64(X), _f64(Y)
+    n = X.shape[0]
+    if Y.shape[0] != n:
+        raise ValueError("hsic_test: X and Y need the same number of rows")
+    ps = np.empty(max(B, 1), dtype=np.float64)
+    out = np.empty(3, dtype=np.float64)
+    cnt = ctypes.c_int64()
+    r = lib().orc_hsic_test(_d(X), _d(Y), n, X.shape[1], Y.shape[1], gamma_x, gamma_y, B, seed,
+                            _d(ps), _d(out), ctypes.byref(cnt), nthreads)
+    if r:
+        raise ValueError("hsic_test failed with code %d" % r)
+    return dict(statistic=float(out[0]), threshold=float(out[1]), p_value=float(out[2]),
+                count_ge=cnt.value, perm_stats=ps[:B].copy())
+

@@ -526,3 +526,130 @@ def test_cross_rejects_too_few_rows():
         oracle.cross(np.zeros((1, 3)), np.zeros((4, 3)), ED)
     with pytest.raises(ValueError):
         oracle.cross(np.zeros((4, 3)), np.zeros((4, 3)), MMD, 0.0)
+
+
+# --------------------------------------------------------------------------- HSIC
+
+def _gauss_kernel(A, gamma):
+    return np.exp(-gamma * cdist(A, A, "sqeuclidean"))
+
+
+def _hsic_u_statistic(K, L):
+    """Unbiased HSIC as the U-statistic of Song et al. (2012, Theorem 2): the mean over
+    ordered 4-tuples of distinct indices of h = (1/24) sum over the 24 orderings (s,t,u,v)
+    of k_st l_st + k_st l_uv - 2 k_st l_su.  Independent of the oracle's closed form."""
+    n = K.shape[0]
+    total = []
+    for quad in itertools.permutations(range(n), 4):
+        h = []
+        for s, t, u, v in itertools.permutations(quad):
+            h.append(K[s, t] * L[s, t] + K[s, t] * L[u, v] - 2.0 * K[s, t] * L[s, u])
+        total.append(math.fsum(h) / 24.0)
+    return math.fsum(total) / len(total)
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7])
+def test_hsic_is_the_u_statistic(n):
+    """The discussion's HSIC (Song et al.'s unbiased estimator) equals its U-statistic over
+    distinct 4-tuples: pins all three terms, their coefficients and the 1/(n(n-3)) scale."""
+    g = _rng(400 + n)
+    X, Y = g.standard_normal((n, 3)), g.standard_normal((n, 2))
+    Y[:, 0] += X[:, 0]  # dependent, so the terms do not nearly cancel
+    K, L = _gauss_kernel(X, 0.4), _gauss_kernel(Y, 0.7)
+    ref = _hsic_u_statistic(K, L)
+    assert abs(oracle.hsic(K, L) - ref) <= 1e-13 * max(1.0, abs(ref)), (oracle.hsic(K, L), ref)
+    # the same through a permutation of y: the U-statistic of the reordered kernel matrix
+    pi = oracle.permutation(n, 3, 1)
+    ref_p = _hsic_u_statistic(K, L[np.ix_(pi, pi)])
+    assert abs(oracle.hsic(K, L, pi) - ref_p) <= 1e-13 * max(1.0, abs(ref_p))
+
+
+def test_hsic_permuted_read_equals_reordered_data():
+    """Reading L through pi is HSIC of (x_i, y_pi(i)): the kernel matrix of the reordered y."""
+    g = _rng(41)
+    n = 40
+    X, Y = g.standard_normal((n, 5)), g.standard_normal((n, 3))
+    K = _gauss_kernel(X, 0.2)
+    for b in range(5):
+        pi = oracle.permutation(n, 9, b)
+        a = oracle.hsic(K, _gauss_kernel(Y, 0.3), pi)
+        c = oracle.hsic(K, _gauss_kernel(Y[pi], 0.3))
+        assert abs(a - c) <= 1e-14 * max(abs(c), 1e-3)
+
+
+def test_hsic_joint_permutation_invariance_and_symmetry():
+    """Relabelling the pairs leaves HSIC unchanged; HSIC(K, L) = HSIC(L, K)."""
+    g = _rng(42)
+    n = 33
+    X, Y = g.standard_normal((n, 4)), g.standard_normal((n, 4))
+    Y += 0.5 * X
+    K, L = _gauss_kernel(X, 0.25), _gauss_kernel(Y, 0.25)
+    s = g.permutation(n)
+    h = oracle.hsic(K, L)
+    assert abs(oracle.hsic(K[np.ix_(s, s)], L[np.ix_(s, s)]) - h) <= 1e-14 * abs(h)
+    assert abs(oracle.hsic(L, K) - h) <= 1e-14 * abs(h)
+
+
+def test_hsic_unbiased_under_independence():
+    """Unbiased estimator: under independence its mean over datasets is 0 (population HSIC)."""
+    g = _rng(43)
+    vals = []
+    for _ in range(1500):
+        X, Y = g.standard_normal((12, 2)), g.standard_normal((12, 2))
+        vals.append(oracle.hsic(_gauss_kernel(X, 0.5), _gauss_kernel(Y, 0.5)))
+    vals = np.array(vals)
+    se = vals.std(ddof=1) / math.sqrt(len(vals))
+    assert abs(vals.mean()) < 4.0 * se, (vals.mean(), se)
+    # and positive in expectation under dependence
+    dep = [oracle.hsic(_gauss_kernel(X, 0.5), _gauss_kernel(X + 0.3 * g.standard_normal(X.shape), 0.5))
+           for X in (g.standard_normal((12, 2)) for _ in range(200))]
+    assert np.mean(dep) > 10 * se
+
+
+def test_permutations_are_uniform_permutations():
+    """Each draw is a permutation; for n = 4 all 24 orders appear equally often (chi-square),
+    and every item is equally likely at every position (n = 7)."""
+    seen = {}
+    for b in range(24000):
+        pi = oracle.permutation(4, 77, b)
+        seen[tuple(pi)] = seen.get(tuple(pi), 0) + 1
+    assert len(seen) == 24
+    from scipy.stats import chisquare
+    assert chisquare(list(seen.values())).pvalue > 1e-3
+    pos = np.zeros((7, 7))
+    for b in range(7000):
+        pi = oracle.permutation(7, 5, b)
+        assert sorted(pi.tolist()) == list(range(7))
+        pos[np.arange(7), pi] += 1
+    assert chisquare(pos.ravel()).pvalue > 1e-3
+    # the stream depends on the seed and on b
+    assert not np.array_equal(oracle.permutation(50, 1, 0), oracle.permutation(50, 2, 0))
+    assert not np.array_equal(oracle.permutation(50, 1, 0), oracle.permutation(50, 1, 1))
+
+
+def test_hsic_test_null_uniform_and_detects_dependence():
+    """Permutation test: p-values roughly uniform under independence, small under a clear
+    dependence; p in [1/(B+1), 1] with the identity as threshold."""
+    from scipy.stats import kstest
+    g = _rng(44)
+    ps = []
+    for r in range(150):
+        X, Y = g.standard_normal((20, 2)), g.standard_normal((20, 3))
+        res = oracle.hsic_test(X, Y, 99, r, 0.5, 0.3)
+        assert 1.0 / 100 <= res["p_value"] <= 1.0
+        assert res["count_ge"] == int(np.sum(res["perm_stats"] >= res["threshold"]))
+        ps.append(res["p_value"])
+    assert kstest(ps, "uniform").pvalue > 1e-3
+    X = g.standard_normal((40, 2))
+    Y = np.column_stack([X[:, 0] ** 2, X[:, 1]]) + 0.2 * g.standard_normal((40, 2))
+    assert oracle.hsic_test(X, Y, 199, 1, 0.5, 0.5)["p_value"] <= 0.01
+
+
+def test_hsic_rejects_bad_input():
+    X = np.zeros((3, 2))
+    with pytest.raises(ValueError):
+        oracle.hsic_test(X, X, 10, 1, 1.0, 1.0)
+    with pytest.raises(ValueError):
+        oracle.hsic_test(np.zeros((5, 2)), np.zeros((6, 2)), 10, 1, 1.0, 1.0)
+    with pytest.raises(ValueError):
+        oracle.hsic_test(np.zeros((5, 2)), np.zeros((5, 2)), 10, 1, 0.0, 1.0)
