@@ -176,6 +176,48 @@ etest_status etest_standard(const etest_request* req, void* stream, etest_result
    2 split stream, 5 per-split sums, 6 statistics and p-value. */
 etest_status etest_precomputed(const etest_request* req, void* stream, etest_result* out);
 
+/* ---- HSIC independence permutation test (the extension of the paper's discussion) ----
+   Paired samples (x_i, y_i), i < n: X is n-by-p and Y n-by-q, row-major, device buffers
+   (double for ETEST_PREC_F64, float otherwise).  The Gaussian kernel matrices K of x and
+   L of y (exp(-gamma ||a - b||^2), gamma_x for x and gamma_y for y) are computed once, on
+   the same staging and Gram kernels as the two-sample blocks; each permutation pi of the y
+   sample then takes one pass over their n^2 entries.  With Kt = K - diag(K), Lt likewise,
+   the statistic is the unbiased HSIC of Song et al. (2012):
+     HSIC = [tr(Kt Lt_pi) + (1^T Kt 1)(1^T Lt 1) / ((n-1)(n-2)) - 2/(n-2) 1^T Kt Lt_pi 1]
+            / (n (n-3)),   Lt_pi[i][j] = Lt[pi_i][pi_j].
+   Permutation b orders the items 0..n-1 by a 64-bit Philox4x32-10 key (key (seed mod 2^32,
+   seed div 2^32), counter (t div 2, b mod 2^32, b div 2^32, 1); even t takes words 0,1,
+   odd t words 2,3, low word first), ties by index.  The identity permutation, evaluated by
+   the same code, is both the reported statistic and the threshold; p = (1 + #{b :
+   HSIC_b >= threshold}) / (1 + B).  4 <= n <= 4096.  prec: ETEST_PREC_F64 or ETEST_PREC_F32
+   (the estimator is a small difference of three large terms -- on high-dimensional data
+   about 1e-5 of the kernel entries under independence -- which the BF16 form's 8-bit
+   coordinates cannot resolve; it is rejected with EINVAL). */
+typedef struct {
+  int32_t prec;          /* etest_prec                                                     */
+  int32_t reserved;      /* must be 0                                                      */
+  int64_t n, p, q;       /* pairs, dimension of x, dimension of y                          */
+  int64_t B;             /* permutations, >= 0                                             */
+  uint64_t seed;         /* permutation stream seed                                        */
+  double gamma_x;        /* kernel on x: exp(-gamma_x ||a - b||^2), > 0                     */
+  double gamma_y;        /* kernel on y, > 0                                               */
+  const void* X;         /* n*p row-major                                                  */
+  const void* Y;         /* n*q row-major                                                  */
+  double* perm_stats;    /* [B] HSIC of each permutation (device), or NULL                 */
+} etest_hsic_request;
+
+/* The HSIC permutation test, synchronous on `stream`; out: host struct (n_refined counts
+   the refined pairs of both Grams in the BF16 form).  Errors: EINVAL (arguments), ENONFINITE
+   (NaN / Inf input; perm_stats untouched), ENOMEM, EDEVICE.  Stage timing: 0 staging,
+   1 blocks, 2 permutations, 3 dense matrices and row sums, 5 per-permutation terms,
+   6 statistics and p-value. */
+etest_status etest_hsic(const etest_hsic_request* req, void* stream, etest_result* out);
+
+/* Permutations b0 .. b0+count-1 of the HSIC test's stream: perms[(b - b0) * n + i] = the item
+   at position i (device, count*n int32).  1 <= n <= 4096. */
+etest_status etest_permutations(int64_t n, uint64_t seed, int64_t b0, int64_t count,
+                                int32_t* perms, void* stream);
+
 /* n independent tests in one batched pass: every stage is one launch covering all tests,
    and the launch sequence is captured once into a HIP graph and replayed while the same
    request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,

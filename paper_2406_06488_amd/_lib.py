@@ -37,6 +37,12 @@ class Request(ctypes.Structure):
                 ("perm_stats", c_vp)]
 
 
+class HsicRequest(ctypes.Structure):
+    _fields_ = [("prec", c_i32), ("reserved", c_i32), ("n", c_i64), ("p", c_i64), ("q", c_i64),
+                ("B", c_i64), ("seed", c_u64), ("gamma_x", c_dbl), ("gamma_y", c_dbl),
+                ("X", c_vp), ("Y", c_vp), ("perm_stats", c_vp)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", c_i64), ("max_resident", c_i32), ("max_queue", c_i32),
                 ("chunk_updates", c_i64)]
@@ -55,6 +61,8 @@ SIGNATURES = [
     ("etest_run", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
     ("etest_cross", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(CrossResult)]),
     ("etest_standard", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
+    ("etest_hsic", c_i32, [ctypes.POINTER(HsicRequest), c_vp, ctypes.POINTER(Result)]),
+    ("etest_permutations", c_i32, [c_i64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     ("etest_precomputed", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
     ("ed_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("mmd_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),

@@ -137,6 +137,38 @@ def precomputed(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats
     return _baseline("etest_precomputed", X, Y, B, seed, kind, prec, gamma, with_perm_stats)
 
 
+def hsic_request(X, Y, B, seed, gamma_x, gamma_y, prec="f32", perm_stats=None):
+    return _lib.HsicRequest(_prec(prec), 0, X.shape[0], X.shape[1], Y.shape[1], B, seed,
+                            gamma_x, gamma_y, X.data_ptr(), Y.data_ptr(),
+                            perm_stats.data_ptr() if perm_stats is not None else None)
+
+
+def hsic(X, Y, B, seed, gamma_x, gamma_y, prec="f32", with_perm_stats=True):
+    """HSIC independence permutation test on paired device rows X (n x p), Y (n x q),
+    synchronous.  Returns run()'s result fields; perm_stats (HSIC of each permutation of
+    the y sample) stays on the device."""
+    import torch
+    _check_dev(X, Y, prec)
+    if X.shape[0] != Y.shape[0]:
+        raise ValueError("hsic: X and Y need the same number of rows")
+    ps = torch.empty(max(B, 1), dtype=torch.float64, device=X.device) if with_perm_stats else None
+    req = hsic_request(X, Y, B, seed, gamma_x, gamma_y, prec, ps)
+    r = Result()
+    check(_lib.load().etest_hsic(ctypes.byref(req), _stream(), ctypes.byref(r)))
+    out = r.as_dict()
+    out["perm_stats"] = ps[:B] if ps is not None else None
+    return out
+
+
+def permutations(n, seed, b0, count, device="cuda"):
+    """Permutations b0 .. b0+count-1 of the HSIC test's stream, as a (count, n) int32 tensor."""
+    import torch
+    out = torch.empty((max(count, 1), n), dtype=torch.int32, device=device)
+    check(_lib.load().etest_permutations(n, seed, b0, count, ctypes.c_void_p(out.data_ptr()),
+                                         _stream()))
+    return out[:count]
+
+
 def cross(X, Y, kind="ed", prec="f32", gamma=0.0):
     """Cross-ED / cross-MMD test (permutation-free) on device tensors, synchronous.
     Returns dict(statistic, sigma, z, p_value, n_refined)."""

@@ -35,6 +35,8 @@ constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
 constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
 constexpr int FLAG_COUNT = 4;        // int32 index of the 64-bit (count, finished WGs) word
 constexpr int FLAG_WORDS = 8;
+constexpr int HSIC_NMAX = 4096;      // HSIC test: largest n (one sort and one kernel row in LDS)
+constexpr int HSIC_RB = 8;           // HSIC test: rows of Kt per workgroup of the term pass
 constexpr int PC_ROWS = 32;          // pre-computation test: tile rows per strip
 constexpr int PC_STRIPS = TILE / PC_ROWS;
 
@@ -221,6 +223,22 @@ __host__ __device__ inline uint32_t f32_to_e4m3(float x) {
     if (code > 0x7Eu) code = 0x7Eu;
   }
   return code ? (sign | code) : 0u;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4 x 32 S-box with
+// the published multipliers and Weyl key increments.  Counter c, key (k0, k1).
+__device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    // one 32 x 32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
 }
 
 // Round-to-nearest-even float -> bf16 bits (finite inputs).

@@ -1203,9 +1203,136 @@ static etest_status run_precomputed(const etest_request& r, hipStream_t st, etes
   return rs;
 }
 
+// HSIC independence test: the Gaussian kernel matrices of x and of y as two one-sample Grams
+// in one batch (staging and blocks only), then dense zero-diagonal copies, row sums, the
+// permutations, the per-permutation terms, the statistics and the p-value.
+// Stage timing (etest_profile_enable): 0 staging, 1 blocks, 2 permutations, 3 dense
+// matrices and row sums, 5 per-permutation terms, 6 statistics + p-value.
+static etest_status run_hsic(const etest_hsic_request& h, hipStream_t st, etest_result* out) {
+  init_pool_once();
+  const int64_t n = h.n, B = h.B, nperm = h.B + 1;
+  const bool f64 = h.prec == ETEST_PREC_F64;
+  etest_request rx{}, ry{};
+  rx.kind = ry.kind = ETEST_MMD;
+  rx.prec = ry.prec = h.prec;
+  rx.nx = ry.nx = n;
+  rx.ny = ry.ny = 0;  // one sample: the Gram covers the x (or y) rows alone
+  rx.p = h.p;
+  ry.p = h.q;
+  rx.gamma = h.gamma_x;
+  ry.gamma = h.gamma_y;
+  rx.X = rx.Y = h.X;
+  ry.X = ry.Y = h.Y;
+  Batch b;
+  b.plans.push_back(make_plan(rx, 0, PLAN_BLOCKS));
+  b.plans.push_back(make_plan(ry, 0, PLAN_BLOCKS));
+  const int64_t nblk = (n + HSIC_RB - 1) / HSIC_RB;
+  const size_t el = f64 ? 8 : 4;
+  enum { H_KX, H_KY, H_RX, H_RY, H_HS, H_FLAGS, H_PERMS, H_PART, H_STATS, H_RES, H_N };
+  size_t sz[H_N] = {(size_t)(n * n) * el, (size_t)(n * n) * el, (size_t)n * 8, (size_t)n * 8,
+                    2 * 8, FLAG_WORDS * 4, (size_t)(nperm * n) * 4, (size_t)(nperm * nblk) * 16,
+                    (size_t)nperm * 8, sizeof(DevResult)};
+  size_t off[H_N], total = 0;
+  for (int k = 0; k < H_N; ++k) {
+    off[k] = total;
+    total += align256(sz[k]);
+  }
+  void* aux = nullptr;
+  hipError_t e = hipMallocAsync(&aux, total, st);
+  if (e != hipSuccess || !aux) {
+    (void)hipGetLastError();
+    return set_error(ETEST_ENOMEM, "HSIC test buffers of " + std::to_string(total) + " bytes");
+  }
+  char* a = (char*)aux;
+  etest_status s = place_batch(&b, st, true);
+  if (s != ETEST_OK) {
+    (void)hipFreeAsync(aux, st);
+    return s;
+  }
+  double* rxs = (double*)(a + off[H_RX]);
+  double* rys = (double*)(a + off[H_RY]);
+  double* hs = (double*)(a + off[H_HS]);
+  int32_t* flags = (int32_t*)(a + off[H_FLAGS]);
+  int32_t* perms = (int32_t*)(a + off[H_PERMS]);
+  double* part = (double*)(a + off[H_PART]);
+  double* stats = (double*)(a + off[H_STATS]);
+  DevResult* d_res = (DevResult*)(a + off[H_RES]);
+  const TestDesc* D = b.d_descs;
+  auto offs = [&](Slot k) { return b.d_offs + (size_t)k * 3; };
+  auto tot = [&](Slot k) { return b.offs[(size_t)k * 3 + 2]; };
+  const StageEvents* ev = profile_events();
+  auto mark = [&](int k, bool begin) {
+    if (ev && (ev->mask >> k & 1u)) (void)hipEventRecord(begin ? ev->begin[k] : ev->end[k], st);
+  };
+  launch_clear_flags(st, D, nullptr, 2);
+  mark(0, true);
+  launch_colpart(tot(S_COLPART), st, D, offs(S_COLPART), 2);
+  launch_colmean(tot(S_COLMEAN), st, D, offs(S_COLMEAN), 2);
+  launch_stage(tot(S_STAGE), st, D, offs(S_STAGE), 2);
+  mark(0, false);
+  mark(1, true);
+  launch_gram(PREC_F64, tot(S_GRAM_F64), st, D, offs(S_GRAM_F64), 2, false);
+  launch_gram(PREC_F32, tot(S_GRAM_F32), st, D, offs(S_GRAM_F32), 2, false);
+  launch_gram(PREC_BF16R, tot(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 2, false);
+  mark(1, false);
+  mark(2, true);
+  launch_permgen(n, h.seed, 0, B, nperm, perms, st);
+  mark(2, false);
+  mark(3, true);
+  launch_hsic_prep(f64, D, n, a + off[H_KX], a + off[H_KY], rxs, rys, hs, flags, st);
+  mark(3, false);
+  mark(5, true);
+  launch_hsic_terms(f64, a + off[H_KX], a + off[H_KY], n, perms, nperm, rxs, rys, part, st);
+  mark(5, false);
+  mark(6, true);
+  launch_hsic_stat(part, n, nperm, hs, stats, st);
+  launch_count(stats, B, flags, h.perm_stats, d_res, st);
+  mark(6, false);
+  etest_status rs = finish_baseline(d_res, &b, aux, st, hipSuccess, "HSIC test", out);
+  profile_collect();
+  return rs;
+}
+
+static etest_status validate_hsic(const etest_hsic_request& h) {
+  // The unbiased HSIC is a small difference of three large terms (on high-dimensional data
+  // about 1e-5 of the kernel entries under independence): 8-bit coordinates cannot carry it,
+  // so the test has the FP64 and FP32 forms only.
+  if (h.prec != ETEST_PREC_F64 && h.prec != ETEST_PREC_F32)
+    return set_error(ETEST_EINVAL, "HSIC test: prec must be ETEST_PREC_F64 or ETEST_PREC_F32");
+  if (h.n < 4 || h.n > HSIC_NMAX)
+    return set_error(ETEST_EINVAL, "HSIC test needs 4 <= n <= " + std::to_string(HSIC_NMAX));
+  if (h.p < 1 || h.q < 1 || h.p > 2147483647LL || h.q > 2147483647LL)
+    return set_error(ETEST_EINVAL, "p and q must be >= 1");
+  if (h.B < 0 || h.B >= 2147483647LL) return set_error(ETEST_EINVAL, "B out of range");
+  if (!(h.gamma_x > 0.0) || !(h.gamma_y > 0.0) || !std::isfinite(h.gamma_x) ||
+      !std::isfinite(h.gamma_y))
+    return set_error(ETEST_EINVAL, "gamma_x and gamma_y must be finite and > 0");
+  if (!h.X || !h.Y) return set_error(ETEST_EINVAL, "X and Y must not be NULL");
+  if (h.reserved != 0) return set_error(ETEST_EINVAL, "reserved field must be 0");
+  return ETEST_OK;
+}
+
 }  // namespace et
 
 extern "C" {
+
+etest_status etest_hsic(const etest_hsic_request* req, void* stream, etest_result* out) {
+  if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
+  etest_status s = validate_hsic(*req);
+  if (s != ETEST_OK) return s;
+  return run_hsic(*req, (hipStream_t)stream, out);
+}
+
+etest_status etest_permutations(int64_t n, uint64_t seed, int64_t b0, int64_t count,
+                                int32_t* perms, void* stream) {
+  if (n < 1 || n > HSIC_NMAX) return set_error(ETEST_EINVAL, "permutations need 1 <= n <= " + std::to_string(HSIC_NMAX));
+  if (b0 < 0 || count < 0 || !perms) return set_error(ETEST_EINVAL, "bad range or NULL perms");
+  hipStream_t st = (hipStream_t)stream;
+  launch_permgen(n, seed, b0, count, count, perms, st);
+  HIP_OK(hipGetLastError(), "permutations launch");
+  HIP_OK(hipStreamSynchronize(st), "permutations");
+  return ETEST_OK;
+}
 
 etest_status etest_standard(const etest_request* req, void* stream, etest_result* out) {
   if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");

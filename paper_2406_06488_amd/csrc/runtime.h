@@ -39,6 +39,15 @@ void launch_precomp(bool f64, const TestDesc* d, int64_t ntiles, int64_t B, doub
                     hipStream_t st);
 void launch_precomp_stat(const TestDesc* d, int64_t ntiles, int64_t B, const double* part,
                          double* stats, hipStream_t st);
+void launch_permgen(int64_t n, uint64_t seed, int64_t b0, int64_t count, int64_t total,
+                    int32_t* perms, hipStream_t st);
+void launch_hsic_prep(bool f64, const TestDesc* d, int64_t n, void* kx, void* ky, double* rx,
+                      double* ry, double* hs, int32_t* flags, hipStream_t st);
+void launch_hsic_terms(bool f64, const void* kx, const void* ky, int64_t n, const int32_t* perms,
+                       int64_t nperm, const double* rx, const double* ry, double* part,
+                       hipStream_t st);
+void launch_hsic_stat(const double* part, int64_t n, int64_t nperm, const double* hs,
+                      double* stats, hipStream_t st);
 void launch_unpack(bool f64, int64_t elems, hipStream_t st, const TestDesc* d, void* xx, void* yy,
                    void* xy);
 

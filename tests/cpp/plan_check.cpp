@@ -29,6 +29,12 @@ void launch_collect(const TestDesc*, int, int64_t, int64_t, double*, int32_t*, h
 void launch_count(const double*, int64_t, const int32_t*, double*, DevResult*, hipStream_t) {}
 void launch_precomp(bool, const TestDesc*, int64_t, int64_t, double*, hipStream_t) {}
 void launch_precomp_stat(const TestDesc*, int64_t, int64_t, const double*, double*, hipStream_t) {}
+void launch_permgen(int64_t, uint64_t, int64_t, int64_t, int64_t, int32_t*, hipStream_t) {}
+void launch_hsic_prep(bool, const TestDesc*, int64_t, void*, void*, double*, double*, double*,
+                      int32_t*, hipStream_t) {}
+void launch_hsic_terms(bool, const void*, const void*, int64_t, const int32_t*, int64_t,
+                       const double*, const double*, double*, hipStream_t) {}
+void launch_hsic_stat(const double*, int64_t, int64_t, const double*, double*, hipStream_t) {}
 }  // namespace et
 
 using namespace et;
@@ -184,6 +190,22 @@ int main() {
               check_mode_plan(r, PLAN_PRECOMP);
             }
           }
+  // one-sample plans of the HSIC test (ny = 0: the Gram covers the rows of one sample)
+  for (int64_t n : {4, 127, 128, 129, 1000, 4096})
+    for (int prec : precs) {
+      etest_request r{};
+      r.kind = ETEST_MMD;
+      r.prec = prec;
+      r.nx = n;
+      r.ny = 0;
+      r.p = 37;
+      r.gamma = 0.1;
+      r.X = r.Y = (const void*)0x1000;
+      check_mode_plan(r, PLAN_BLOCKS);
+      const TestPlan P = make_plan(r, 0, PLAN_BLOCKS);
+      CHECK(P.d.ty == 0 && P.d.nt == P.d.tx && P.d.tx * TILE >= n, "one-sample tiles n %lld",
+            (long long)n);
+    }
   std::printf("%s (%d failures)\n", failures ? "FAILED" : "ok", failures);
   return failures ? 1 : 0;
 }
