@@ -22,6 +22,8 @@ Workloads (--workload):
   studies         Section 5.2 null and power studies (efficient test vs cross-ED)
   timing          Section 5.1 computing-time experiments: standard, pre-computation,
                   efficient and cross-ED tests, B = 200, FP64 and FP32 forms
+  hsic            HSIC independence permutation test (the discussion's extension), FP32,
+                  n = 2000 and 4096 pairs, p = q = 500, B = 200
 
 Prints ONE JSON line on stdout.  Per-stage device times come from HIP events recorded by
 the library on the launch stream.
@@ -141,7 +143,9 @@ KERNEL_SOURCES = {"k_gram_f32": ["k_gram.hip", "common.h"],
                   "k_gram_bf16": ["k_gram.hip", "common.h"],
                   "k_dist_f64": ["k_gram.hip", "common.h"],
                   "k_perm_mfma": ["k_perm.hip", "common.h"],
-                  "k_perm_f64": ["k_perm.hip", "common.h"]}
+                  "k_perm_f64": ["k_perm.hip", "common.h"],
+                  "k_precomp": ["k_baseline.hip", "common.h"],
+                  "k_hsic_terms": ["k_hsic.hip", "common.h"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
 
 
@@ -541,6 +545,77 @@ def run_timing(args):
     return line
 
 
+def run_hsic(args):
+    """HSIC independence permutation test (the extension in the paper's discussion), FP32
+    form: n pairs, x and y of dimension p = q = 500, Gaussian kernels with gamma = 1/p,
+    B = 200 permutations (the paper's count), dependence through tanh of the first
+    coordinates.  n = 2000 (headline) and n = 4096 (the largest supported).  Steps are whole
+    tests; the per-stage times come from HIP events on the launch stream."""
+    import numpy as np
+    import torch
+
+    from paper_2406_06488_amd import api
+    B, p = 200, 500
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    rows = {}
+    head = None
+    for n in [int(v) for v in args.hsic_n.split(",") if v]:
+        X = torch.randn(n, p, generator=gen, device="cuda")
+        Y = torch.randn(n, p, generator=gen, device="cuda")
+        Y[:, :10] += 0.2 * torch.tanh(X[:, :10])
+
+        def step():
+            return api.hsic(X, Y, B, 1, 1.0 / p, 1.0 / p, "f32", with_perm_stats=False)
+
+        elapsed, live, prof, res = timed(step, args.steps, args.warmup)
+        stage = per_launch(prof)
+        terms_ms = per_launch(live)["resampling"]
+        entries = (B + 1) * n * n
+        rows[str(n)] = {"ms_per_test": 1e3 * elapsed / args.steps, "p_value": res["p_value"],
+                        "statistic": res["statistic"],
+                        "stage_ms": {k: round(v, 5) for k, v in stage.items()},
+                        "terms_ms_live": terms_ms,
+                        "terms_gather_GBs": entries * 8 / (terms_ms * 1e-3) / 1e9}
+        log("hsic n", n, rows[str(n)])
+        if head is None:
+            head = (n, elapsed, terms_ms, entries, X, Y)
+    n, elapsed, terms_ms, entries, X, Y = head
+    achieved = entries * 8 / (terms_ms * 1e-3) / 1e9
+    line = base_line(args, "hsic_f32_n2000_p500_B200", args.steps / elapsed, elapsed, args.steps,
+                     "f32", {"n": n, "p": p, "q": p, "B": B, "kernel": "gaussian, gamma = 1/p"})
+    line.update({"metric": "HSIC permutation tests/s (n = 2000, p = q = 500, B = 200)",
+                 "unit": "tests/s", "sizes": rows,
+                 "roofline": {"bound": "hbm", "kernel": "k_hsic_terms<float>",
+                              "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                              "algorithmic": "8 bytes (one Kt and one gathered Lt entry) per "
+                                             "entry and permutation: (B+1) n^2 x 8 = %.4g per "
+                                             "launch" % (entries * 8),
+                              "frac": achieved / PEAK["hbm_GBs"],
+                              "traffic": measured_traffic("k_hsic_terms<float>",
+                                                          "hsic_f32_n2000_p500_B200")}})
+    if not args.no_cpu_baseline:
+        import oracle
+        Xh, Yh = X.double().cpu().numpy(), Y.double().cpu().numpy()
+        bs = 4
+        log("cpu baseline (oracle) ...")
+        t0 = time.perf_counter()
+        oracle.hsic_test(Xh, Yh, bs, 1, 1.0 / p, 1.0 / p)
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.hsic_test(Xh, Yh, 0, 1, 1.0 / p, 1.0 / p)
+        d0 = time.perf_counter() - t0
+        per_perm = max(dt - d0, 1e-9) / bs
+        line["cpu_baseline"] = {"value": 1.0 / (d0 + per_perm * B), "unit": "tests/s",
+                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+                                "kind": "oracle",
+                                "sample": "kernel matrices and identity, then %d permutations "
+                                          "at n = %d (projected to B = %d)" % (bs, n, B)}
+    else:
+        line["cpu_baseline"] = None
+    return line
+
+
 def run_serving(args):
     import numpy as np
     import torch
@@ -640,11 +715,13 @@ def main():
                     help="studies: fraction of the paper's replication counts")
     ap.add_argument("--workload", default="plain_f32",
                     choices=["plain_f32", "small_f64", "precision_bf16", "batched", "serving",
-                             "cross_f32", "cross_bf16", "studies", "timing"])
+                             "cross_f32", "cross_bf16", "studies", "timing", "hsic"])
     ap.add_argument("--timing-reps", type=int, default=20,
                     help="timing: replications per shape and test (standard test: half)")
     ap.add_argument("--timing-precs", default="f64,f32",
                     help="timing: comma-separated forms to time")
+    ap.add_argument("--hsic-n", default="2000,4096",
+                    help="hsic: comma-separated pair counts (the first one is the headline)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=200.0)
@@ -673,6 +750,8 @@ def main():
         line = run_studies(args)
     elif args.workload == "timing":
         line = run_timing(args)
+    elif args.workload == "hsic":
+        line = run_hsic(args)
     else:
         line = run_serving(args)
     print(json.dumps(line), flush=True)
