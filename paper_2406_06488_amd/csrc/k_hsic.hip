@@ -165,7 +165,11 @@ __global__ void __launch_bounds__(256) k_hsic_terms(const T* __restrict__ kx,
                                                     double* __restrict__ part) {
   __shared__ T lrow[HSIC_NMAX];
   __shared__ double red[256][2];
-  const int64_t b = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  // Work unit u = blk * nperm + b, numbered so that each XCD takes runs of consecutive units:
+  // a run covers one row block for several permutations, whose Kt rows its L2 then serves.
+  const int64_t nperm = gridDim.x / nblk;
+  const int64_t u = xcd_grouped(blockIdx.x, gridDim.x);
+  const int64_t blk = u / nperm, b = u % nperm;
   const int32_t* pi = perms + b * n;
   const int tid = threadIdx.x;
   constexpr int PER = HSIC_NMAX / 256;
@@ -215,21 +219,35 @@ __global__ void __launch_bounds__(256) k_hsic_terms(const T* __restrict__ kx,
   }
 }
 
-// HSIC of permutation b from its row-block partials (compensated, in block order).
-__global__ void __launch_bounds__(256) k_hsic_stat(const double* __restrict__ part, int64_t nblk,
-                                                   int64_t nperm, int64_t n,
-                                                   const double* __restrict__ hs,
-                                                   double* __restrict__ stats) {
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b >= nperm) return;
+// HSIC of 64 permutations per workgroup from their row-block partials: 16 groups of waves
+// each take every 16th block (compensated), then wave 0 adds the 16 group sums in order.
+constexpr int HS_GROUPS = 16;
+__global__ void __launch_bounds__(64 * HS_GROUPS) k_hsic_stat(const double* __restrict__ part,
+                                                              int64_t nblk, int64_t nperm,
+                                                              int64_t n,
+                                                              const double* __restrict__ hs,
+                                                              double* __restrict__ stats) {
+  __shared__ double red[2][HS_GROUPS][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 64 + c;
   Hsum t1, t3;
-  for (int64_t k = 0; k < nblk; ++k) {
-    t1.add(part[(b * nblk + k) * 2]);
-    t3.add(part[(b * nblk + k) * 2 + 1]);
+  if (b < nperm)
+    for (int64_t k = g; k < nblk; k += HS_GROUPS) {
+      t1.add(part[(b * nblk + k) * 2]);
+      t3.add(part[(b * nblk + k) * 2 + 1]);
+    }
+  red[0][g][c] = t1.value();
+  red[1][g][c] = t3.value();
+  __syncthreads();
+  if (g != 0 || b >= nperm) return;
+  Hsum u1, u3;
+  for (int q = 0; q < HS_GROUPS; ++q) {
+    u1.add(red[0][q][c]);
+    u3.add(red[1][q][c]);
   }
   const double dn = (double)n;
   const double t2 = hs[0] * hs[1];
-  stats[b] = (t1.value() + t2 / ((dn - 1.0) * (dn - 2.0)) - 2.0 * t3.value() / (dn - 2.0)) /
+  stats[b] = (u1.value() + t2 / ((dn - 1.0) * (dn - 2.0)) - 2.0 * u3.value() / (dn - 2.0)) /
              (dn * (dn - 3.0));
 }
 
@@ -269,8 +287,8 @@ void launch_hsic_terms(bool f64, const void* kx, const void* ky, int64_t n, cons
 void launch_hsic_stat(const double* part, int64_t n, int64_t nperm, const double* hs,
                       double* stats, hipStream_t st) {
   const int64_t nblk = (n + HSIC_RB - 1) / HSIC_RB;
-  hipLaunchKernelGGL(k_hsic_stat, dim3((unsigned)((nperm + 255) / 256)), dim3(256), 0, st, part,
-                     nblk, nperm, n, hs, stats);
+  hipLaunchKernelGGL(k_hsic_stat, dim3((unsigned)((nperm + 63) / 64)), dim3(64 * HS_GROUPS), 0, st,
+                     part, nblk, nperm, n, hs, stats);
 }
 
 }  // namespace et
