@@ -1167,6 +1167,11 @@ static etest_status run_precomputed(const etest_request& r, hipStream_t st, etes
   init_pool_once();
   Batch b;
   b.plans.push_back(make_plan(r, 0, PLAN_PRECOMP));
+  // one workgroup per (stored tile, 32-row strip, 64 split columns)
+  const int64_t groups = (r.B + 1 + 63) / 64;
+  if ((int64_t)b.plans[0].d.ntiles * PC_STRIPS > 2147483647LL / groups)
+    return set_error(ETEST_EINVAL, "pre-computation test: tiles x strips x split groups must "
+                                   "stay below 2^31");
   etest_status s = place_batch(&b, st, true);
   if (s != ETEST_OK) return s;
   const TestDesc& d = b.descs[0];
@@ -1309,6 +1314,11 @@ static etest_status validate_hsic(const etest_hsic_request& h) {
     return set_error(ETEST_EINVAL, "gamma_x and gamma_y must be finite and > 0");
   if (!h.X || !h.Y) return set_error(ETEST_EINVAL, "X and Y must not be NULL");
   if (h.reserved != 0) return set_error(ETEST_EINVAL, "reserved field must be 0");
+  // the term pass launches one workgroup per (permutation, block of HSIC_RB rows)
+  const int64_t nblk = (h.n + HSIC_RB - 1) / HSIC_RB;
+  if ((h.B + 1) > 2147483647LL / nblk)
+    return set_error(ETEST_EINVAL, "HSIC test: (B + 1) * ceil(n / " + std::to_string(HSIC_RB) +
+                                       ") must stay below 2^31");
   return ETEST_OK;
 }
 

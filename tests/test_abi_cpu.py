@@ -36,6 +36,35 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.Result) == 48
     assert ctypes.sizeof(_lib.Request) == 8 + 5 * 8 + 8 + 3 * 8
     assert ctypes.sizeof(_lib.ServerConfig) == 24
+    assert ctypes.sizeof(_lib.CrossResult) == 40
+    assert ctypes.sizeof(_lib.HsicRequest) == 8 + 5 * 8 + 2 * 8 + 3 * 8
+
+
+def test_next_row_calls_reject_before_device():
+    """The baseline, cross and HSIC entry points check their arguments on the host first."""
+    L = _lib.load()
+    r = _lib.Result()
+    bad = _lib.Request(0, _lib.PREC_F32, 0, 5, 3, 10, 1, 0.0, 8, 8, None)  # nx = 0
+    for fn in (L.etest_standard, L.etest_precomputed):
+        assert fn(ctypes.byref(bad), None, ctypes.byref(r)) == _lib.EINVAL
+        assert fn(None, None, ctypes.byref(r)) == _lib.EINVAL
+    cr = _lib.CrossResult()
+    one = _lib.Request(0, _lib.PREC_F32, 1, 5, 3, 0, 1, 0.0, 8, 8, None)  # nx = 1: no halves
+    assert L.etest_cross(ctypes.byref(one), None, ctypes.byref(cr)) == _lib.EINVAL
+
+    def hreq(**kw):
+        f = dict(prec=_lib.PREC_F32, reserved=0, n=10, p=3, q=2, B=10, seed=1, gamma_x=0.5,
+                 gamma_y=0.5, X=8, Y=8, perm_stats=None)
+        f.update(kw)
+        return _lib.HsicRequest(*[f[k] for k, _ in _lib.HsicRequest._fields_])
+
+    for kw in (dict(n=3), dict(n=4097), dict(q=0), dict(prec=_lib.PREC_BF16_REFINED),
+               dict(gamma_x=0.0), dict(gamma_y=float("nan")), dict(B=-1), dict(reserved=1),
+               dict(X=None), dict(B=2 ** 30)):
+        assert L.etest_hsic(ctypes.byref(hreq(**kw)), None, ctypes.byref(r)) == _lib.EINVAL, kw
+    assert L.etest_permutations(0, 1, 0, 1, 8, None) == _lib.EINVAL
+    assert L.etest_permutations(5000, 1, 0, 1, 8, None) == _lib.EINVAL
+    assert L.etest_permutations(5, 1, -1, 1, 8, None) == _lib.EINVAL
 
 
 @pytest.mark.parametrize("args", [

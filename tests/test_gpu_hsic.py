@@ -175,4 +175,6 @@ def test_hsic_bad_arguments_rejected():
         req = api.hsic_request(Xd, Yd, 10, 1, 0.3, 0.3, "f32")
         setattr(req, field, value)
         assert fn(ctypes.byref(req), None, ctypes.byref(r)) == _lib.EINVAL, field
+    req = api.hsic_request(Xd, Yd, 2 ** 30, 1, 0.3, 0.3, "f32")  # grid would pass 2^31
+    assert fn(ctypes.byref(req), None, ctypes.byref(r)) == _lib.EINVAL
     assert _lib.load().etest_permutations(0, 1, 0, 1, None, None) == _lib.EINVAL
