@@ -69,7 +69,9 @@ typedef enum {
 
 typedef enum {
   ETEST_PREC_F64 = 0,         /* FP64 inputs, FP64 blocks, FP64 reductions                */
-  ETEST_PREC_F32 = 1,         /* FP32 inputs, FP32 Gram on MFMA, FP32 blocks, FP64 sums   */
+  ETEST_PREC_F32 = 1,         /* FP32 inputs; Gram of FP32 accuracy on fp16 MFMA: each     */
+                              /* centred value as two fp16 (22 bits), three exact products */
+                              /* per term, FP32 accumulation; FP32 blocks, FP64 sums       */
   ETEST_PREC_BF16_REFINED = 2 /* FP32 inputs, BF16 Gram on MFMA with FP32 accumulation,   */
                               /* pairs with d^2 < 1e-3 (|x|^2 + |y|^2) recomputed as a    */
                               /* direct FP32 difference, FP64 sums                        */

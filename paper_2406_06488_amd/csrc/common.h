@@ -3,7 +3,8 @@
 // Data layout in HBM for one test (n_pad = (tx + ty) * TILE):
 //   W      [n_pad][p_pad]   staged operand rows: X rows, zero rows up to a TILE
 //                           boundary, Y rows, zero rows (column-mean centred for
-//                           the FP32/BF16 forms; FP64/FP32/BF16 elements)
+//                           the FP32/BF16 forms; FP64 elements, fp16 pairs (hi, lo) of
+//                           the scaled value for the FP32 form, BF16 elements)
 //   nrm    [n_pad]          squared row norms of the staged rows
 //   D      [ntiles][T][T]   upper tiles (i <= j) of the pooled tile grid: XX upper
 //                           tiles, every XY tile, YY upper tiles -- never a YX tile
@@ -35,6 +36,7 @@ constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
 constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
 constexpr int FLAG_COUNT = 4;        // int32 index of the 64-bit (count, finished WGs) word
 constexpr int FLAG_WORDS = 8;
+constexpr int FLAG_XMAX = 6;         // FP32 form: bits of max |input| (a non-negative float)
 constexpr int HSIC_NMAX = 4096;      // HSIC test: largest n (one sort and one kernel row in LDS)
 constexpr int HSIC_RB = 8;           // HSIC test: rows of Kt per workgroup of the term pass
 constexpr int PC_ROWS = 32;          // pre-computation test: tile rows per strip
@@ -84,7 +86,7 @@ struct TestDesc {
   uint32_t* Z;
   double* part;
   double* pstat;
-  int32_t* flags;    // [0] non-finite input seen, [1] refined pair count
+  int32_t* flags;    // [0] non-finite input seen, [1] refined pair count, [FLAG_XMAX] max |x|
   // flags[FLAG_COUNT..+1]: exceedance count (low half) and finished workgroups (high half)
   double* perm_out;
   DevResult* result;
@@ -223,6 +225,20 @@ __host__ __device__ inline uint32_t f32_to_e4m3(float x) {
     if (code > 0x7Eu) code = 0x7Eu;
   }
   return code ? (sign | code) : 0u;
+}
+
+// FP32 form: the centred operand w is staged as two fp16 values per entry, hi = fp16(w 2^e)
+// and lo = fp16(w 2^e - hi) (together 22 significant bits; every product of two of them is
+// exact in FP32).  max |x| over the input bounds every centred value by 2 max|x| < 2^(ex+1)
+// (max|x| = m 2^ex, 0.5 <= m < 1), so e = 13 - ex keeps |w 2^e| below 2^14, inside fp16's
+// range.  Returns e (0 without a finite positive maximum).
+__device__ inline int f16_split_exponent(const TestDesc& d) {
+  const float m = __uint_as_float((uint32_t)d.flags[FLAG_XMAX]);
+  if (!(m > 0.0f) || !isfinite(m)) return 0;
+  int ex;
+  (void)frexpf(m, &ex);
+  const int e = 13 - ex;
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4 x 32 S-box with

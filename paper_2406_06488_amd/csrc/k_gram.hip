@@ -15,7 +15,6 @@ namespace et {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int LDS_ROW_F32 = 36;   // 32 staged k + 4 pad (floats)
 constexpr int LDS_ROW_BF16 = 72;  // 64 staged k + 8 pad (bf16)
 
 struct TileCtx {
@@ -277,24 +276,36 @@ __device__ inline void gram_epilogue(const TestDesc& d, const TileCtx& c, f32x16
   add_refined(d, refined);
 }
 
-// ---------------------------------------------------------------- FP32 MFMA
-// 4 waves as 2 x 2, each 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x2_f32.
-// Three resident workgroups per CU (register budget <= 168 per lane): 768 slots, so a
-// 2000 + 2000 test's 528 tiles run in a single round.
+// ---------------------------------------------------------------- FP32 form on fp16 MFMA
+// The staged operand holds fp16 pairs (hi, lo) of w 2^e (22 significant bits; see
+// f16_split_exponent).  Each Gram entry is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b
+// (the lo_a lo_b term, 2^-22 of the product, is dropped) with three
+// v_mfma_f32_32x32x16_f16 into one FP32 accumulator: all three products are exact in FP32,
+// so the entry carries the same FP32 accumulation rounding as an FP32 Gram, at the fp16
+// MFMA rate.  The accumulator is scaled back by 2^-2e before the epilogue.
+// 4 waves as 2 x 2, each 64 x 64 = 2 x 2 blocks of 32 x 32; K slices of 32 pairs; the next
+// slice is loaded into registers while the current one is multiplied; the pairs are split
+// into a hi and a lo plane when stored to LDS (40 KB), so three workgroups fit per CU.
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+constexpr int KS16 = 32;                // pairs per K slice
+constexpr int LDS_ROW_F16 = KS16 + 8;   // halves per LDS row (80 bytes)
+
 template <bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-k_gram_f32(const TestDesc* __restrict__ descs,
-                                                  const int64_t* __restrict__ offs, int ntests) {
-  __shared__ __attribute__((aligned(16))) float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F32 ? HALF * TILE_LDS
-                                                                  : 2 * TILE * LDS_ROW_F32];
+k_gram_f16x3(const TestDesc* __restrict__ descs, const int64_t* __restrict__ offs, int ntests) {
+  __shared__ __attribute__((aligned(16))) float smem[HALF * TILE_LDS > 2 * TILE * LDS_ROW_F16
+                                                         ? HALF * TILE_LDS
+                                                         : 2 * TILE * LDS_ROW_F16];
   const int64_t bid = xcd_grouped(blockIdx.x, gridDim.x);
   const int ti = find_test(offs, ntests, bid);
   const TestDesc d = descs[ti];
   const TileCtx c = tile_ctx(d, bid - offs[ti]);
-  const float* Wa = (const float*)d.W + (int64_t)c.i * TILE * d.p_pad;
-  const float* Wb = (const float*)d.W + (int64_t)c.j * TILE * d.p_pad;
-  float* As = smem;
-  float* Bs = smem + TILE * LDS_ROW_F32;
+  const uint32_t* Wa = (const uint32_t*)d.W + (int64_t)c.i * TILE * d.p_pad;
+  const uint32_t* Wb = (const uint32_t*)d.W + (int64_t)c.j * TILE * d.p_pad;
+  uint16_t* Ah = (uint16_t*)smem;
+  uint16_t* Al = Ah + TILE * LDS_ROW_F16;
+  uint16_t* Bh = Al + TILE * LDS_ROW_F16;
+  uint16_t* Bl = Bh + TILE * LDS_ROW_F16;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int wm = w >> 1, wn = w & 1, h = lane >> 5, lr = lane & 31;
   f32x16 acc[2][2];
@@ -302,59 +313,69 @@ k_gram_f32(const TestDesc* __restrict__ descs,
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.0f;
 
-  // the next 32-wide slice is loaded into registers while the current one is multiplied
-  // 1024 float4 per operand and slice: thread tid owns rows (tid >> 3) + 32 s, column
-  // group (tid & 7); the next slice is loaded into registers while the current one is
-  // multiplied.
-  const int lrow = tid >> 3, lc4 = (tid & 7) * 4;
-  const float* ga = Wa + (int64_t)lrow * d.p_pad + lc4;
-  const float* gb = Wb + (int64_t)lrow * d.p_pad + lc4;
+  // 1024 uint4 (4 pairs each) per operand and slice: thread tid owns rows (tid >> 3) + 32 s,
+  // pairs 4 (tid & 7) .. +3
+  const int lrow = tid >> 3, c4 = (tid & 7) * 4;
+  const uint32_t* ga = Wa + (int64_t)lrow * d.p_pad + c4;
+  const uint32_t* gb = Wb + (int64_t)lrow * d.p_pad + c4;
   const int64_t rstep = (int64_t)32 * d.p_pad;
-  float4 pa0 = *(const float4*)(ga), pa1 = *(const float4*)(ga + rstep);
-  float4 pa2 = *(const float4*)(ga + 2 * rstep), pa3 = *(const float4*)(ga + 3 * rstep);
-  float4 pb0 = *(const float4*)(gb), pb1 = *(const float4*)(gb + rstep);
-  float4 pb2 = *(const float4*)(gb + 2 * rstep), pb3 = *(const float4*)(gb + 3 * rstep);
-  for (int k0 = 0; k0 < d.p_pad; k0 += 32) {
+  uint4 pa[4], pb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    pa[s] = *(const uint4*)(ga + s * rstep);
+    pb[s] = *(const uint4*)(gb + s * rstep);
+  }
+  // four pairs -> their four hi halves and four lo halves
+  auto split_store = [&](const uint4 q, uint16_t* hi, uint16_t* lo) {
+    uint2 vh, vl;
+    vh.x = (q.x & 0xFFFFu) | (q.y << 16);
+    vh.y = (q.z & 0xFFFFu) | (q.w << 16);
+    vl.x = (q.x >> 16) | (q.y & 0xFFFF0000u);
+    vl.y = (q.z >> 16) | (q.w & 0xFFFF0000u);
+    *(uint2*)hi = vh;
+    *(uint2*)lo = vl;
+  };
+  for (int k0 = 0; k0 < d.p_pad; k0 += KS16) {
     __syncthreads();
-    float* la = As + lrow * LDS_ROW_F32 + lc4;
-    float* lb = Bs + lrow * LDS_ROW_F32 + lc4;
-    *(float4*)(la) = pa0;
-    *(float4*)(la + 32 * LDS_ROW_F32) = pa1;
-    *(float4*)(la + 64 * LDS_ROW_F32) = pa2;
-    *(float4*)(la + 96 * LDS_ROW_F32) = pa3;
-    *(float4*)(lb) = pb0;
-    *(float4*)(lb + 32 * LDS_ROW_F32) = pb1;
-    *(float4*)(lb + 64 * LDS_ROW_F32) = pb2;
-    *(float4*)(lb + 96 * LDS_ROW_F32) = pb3;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int off = (lrow + 32 * s) * LDS_ROW_F16 + c4;
+      split_store(pa[s], Ah + off, Al + off);
+      split_store(pb[s], Bh + off, Bl + off);
+    }
     __syncthreads();
-    if (k0 + 32 < d.p_pad) {
-      const float* na = ga + k0 + 32;
-      const float* nb2 = gb + k0 + 32;
-      pa0 = *(const float4*)(na);
-      pa1 = *(const float4*)(na + rstep);
-      pa2 = *(const float4*)(na + 2 * rstep);
-      pa3 = *(const float4*)(na + 3 * rstep);
-      pb0 = *(const float4*)(nb2);
-      pb1 = *(const float4*)(nb2 + rstep);
-      pb2 = *(const float4*)(nb2 + 2 * rstep);
-      pb3 = *(const float4*)(nb2 + 3 * rstep);
+    if (k0 + KS16 < d.p_pad) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        pa[s] = *(const uint4*)(ga + k0 + KS16 + s * rstep);
+        pb[s] = *(const uint4*)(gb + k0 + KS16 + s * rstep);
+      }
     }
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      // lane half h supplies staged columns 16h .. 16h+15 (the same for A and B)
-      float4 av[2], bv[2];
+    for (int ks = 0; ks < KS16 / 16; ++ks) {
+      f16x8_t ah[2], al[2], bh[2], bl[2];
+      for (int mb = 0; mb < 2; ++mb) {
+        const int off = (wm * 64 + mb * 32 + lr) * LDS_ROW_F16 + 16 * ks + 8 * h;
+        ah[mb] = *(const f16x8_t*)(Ah + off);
+        al[mb] = *(const f16x8_t*)(Al + off);
+      }
+      for (int nb = 0; nb < 2; ++nb) {
+        const int off = (wn * 64 + nb * 32 + lr) * LDS_ROW_F16 + 16 * ks + 8 * h;
+        bh[nb] = *(const f16x8_t*)(Bh + off);
+        bl[nb] = *(const f16x8_t*)(Bl + off);
+      }
       for (int mb = 0; mb < 2; ++mb)
-        av[mb] = *(const float4*)(As + (wm * 64 + mb * 32 + lr) * LDS_ROW_F32 + 16 * h + 4 * s4);
-      for (int nb = 0; nb < 2; ++nb)
-        bv[nb] = *(const float4*)(Bs + (wn * 64 + nb * 32 + lr) * LDS_ROW_F32 + 16 * h + 4 * s4);
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        for (int mb = 0; mb < 2; ++mb)
-          for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[mb][e], bv[nb][e], acc[mb][nb],
-                                                               0, 0, 0);
+        for (int nb = 0; nb < 2; ++nb) {
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[mb], bh[nb], acc[mb][nb], 0, 0, 0);
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[mb], bl[nb], acc[mb][nb], 0, 0, 0);
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[mb], bh[nb], acc[mb][nb], 0, 0, 0);
+        }
     }
   }
+  const float unscale = ldexpf(1.0f, -2 * f16_split_exponent(d));
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 16; ++e) acc[a][b][e] *= unscale;
   // DUAL: launches that hold a test feeding an MMD test keep the squared distances for two
   // outputs; plain launches turn them into block values at once
   if (DUAL) {
@@ -552,9 +573,9 @@ void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d,
   if (prec == PREC_F64)
     hipLaunchKernelGGL(k_dist_f64, g, b, 0, st, d, offs, n);
   else if (prec == PREC_F32 && dual)
-    hipLaunchKernelGGL(k_gram_f32<true>, g, b, 0, st, d, offs, n);
+    hipLaunchKernelGGL(k_gram_f16x3<true>, g, b, 0, st, d, offs, n);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL(k_gram_f32<false>, g, b, 0, st, d, offs, n);
+    hipLaunchKernelGGL(k_gram_f16x3<false>, g, b, 0, st, d, offs, n);
   else if (dual)
     hipLaunchKernelGGL(k_gram_bf16<true>, g, b, 0, st, d, offs, n);
   else

@@ -19,7 +19,9 @@ __device__ inline double load_in_f64(const TestDesc& d, int64_t t, int k) {
 }
 
 // Partial column sums over chunks of ROWCHUNK pooled rows (FP64).  All ROWCHUNK loads of a
-// thread are issued before the (fixed-order) sum, so they are in flight together.
+// thread are issued before the (fixed-order) sum, so they are in flight together.  The FP32
+// form also takes max |x| over the input (one atomic per wave), which sets the scale of its
+// fp16 operand pairs.
 __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
@@ -28,16 +30,27 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
   const int ncb = (d.p + 255) / 256;
   const int rc = (int)(local / ncb);
   const int k = (int)(local % ncb) * 256 + threadIdx.x;
-  if (k >= d.p) return;
+  const bool ok = k < d.p;
   const int64_t n = (int64_t)d.nx + d.ny;
   const int64_t t0 = (int64_t)rc * ROWCHUNK;
   float v[ROWCHUNK];
 #pragma unroll
-  for (int r = 0; r < ROWCHUNK; ++r) v[r] = t0 + r < n ? load_in_f32(d, t0 + r, k) : 0.0f;
+  for (int r = 0; r < ROWCHUNK; ++r) v[r] = ok && t0 + r < n ? load_in_f32(d, t0 + r, k) : 0.0f;
   double s = 0.0;
+  float mx = 0.0f;
 #pragma unroll
-  for (int r = 0; r < ROWCHUNK; ++r) s += (double)v[r];
-  d.colpart[(int64_t)rc * d.p + k] = s;
+  for (int r = 0; r < ROWCHUNK; ++r) {
+    s += (double)v[r];
+    mx = fmaxf(mx, fabsf(v[r]));  // fmaxf drops NaN; an Inf makes the scale 1 (flagged anyway)
+  }
+  if (ok) d.colpart[(int64_t)rc * d.p + k] = s;
+  if (d.prec == PREC_F32) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+    // non-negative floats order like their bit patterns
+    if ((threadIdx.x & 63) == 0 && mx > 0.0f)
+      atomicMax((unsigned int*)&d.flags[FLAG_XMAX], __float_as_uint(mx));
+  }
 }
 
 // Column means: 64 columns per workgroup, 16 groups of waves each summing every 16th
@@ -66,6 +79,18 @@ __global__ void __launch_bounds__(64 * CM_GROUPS) k_colmean(const TestDesc* __re
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// FP32 form: w -> (hi, lo) with hi = fp16(w 2^e), lo = fp16(w 2^e - hi), packed hi in the
+// low half; *r = (hi + lo) 2^-e, the value the Gram's products see (its norm goes to nrm, so
+// that |a|^2 + |b|^2 - 2 g is formed from one set of operand values).
+__device__ inline uint32_t f16_pair(float w, int e, double* r) {
+  const float hs = ldexpf(w, e);
+  const _Float16 hi = (_Float16)hs;
+  const _Float16 lo = (_Float16)(hs - (float)hi);  // the difference is exact in FP32
+  *r = ldexp((double)(float)hi + (double)(float)lo, -e);
+  return (uint32_t)__builtin_bit_cast(uint16_t, hi) |
+         ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
 }
 
 // One wave per padded pooled row: write W[pos][0..p_pad), nrm[pos]; flag NaN/Inf.
@@ -101,6 +126,7 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
     if (lane == 0) ((double*)d.nrm)[pos] = nrm;
   } else {
     const bool bf = d.prec == PREC_BF16R;
+    const int e = bf ? 0 : f16_split_exponent(d);
     const float* src = t < 0 ? nullptr : pooled_row<float>(d, t);
     // four columns per lane when every row starts on a 16-byte boundary
     const bool vec = (d.p & 3) == 0 && (((uintptr_t)d.X | (uintptr_t)d.Y) & 15) == 0;
@@ -126,9 +152,14 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
           const double r2 = bf16_to_f32(h2), r3 = bf16_to_f32(h3);
           nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
         } else {
-          *(float4*)((float*)d.W + pos * d.p_pad + k) = v;
-          nrm += (((double)v.x * v.x + (double)v.y * v.y) + (double)v.z * v.z) +
-                 (double)v.w * v.w;
+          double r0, r1, r2, r3;
+          uint4 o;
+          o.x = f16_pair(v.x, e, &r0);
+          o.y = f16_pair(v.y, e, &r1);
+          o.z = f16_pair(v.z, e, &r2);
+          o.w = f16_pair(v.w, e, &r3);
+          *(uint4*)((uint32_t*)d.W + pos * d.p_pad + k) = o;
+          nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
         }
       }
     } else {
@@ -145,8 +176,9 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
           const float r = bf16_to_f32(h);
           nrm += (double)r * (double)r;
         } else {
-          ((float*)d.W)[pos * d.p_pad + k] = v;
-          nrm += (double)v * (double)v;
+          double r;
+          ((uint32_t*)d.W)[pos * d.p_pad + k] = f16_pair(v, e, &r);
+          nrm += r * r;
         }
       }
     }
