@@ -77,7 +77,9 @@ static uint64_t tune_generation() {
 // launch would have fewer than 512 workgroups (two per CU), so small tests still spread
 // over the chip.
 static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
-  *cc = r.prec == ETEST_PREC_F64 ? MAX_CC : 2;
+  // the FP64 kernel stages its strip again for every chunk, so grouping chunks in one
+  // workgroup only serialises them: one chunk per workgroup
+  *cc = r.prec == ETEST_PREC_F64 ? 1 : 2;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const int64_t n = r.nx + r.ny;
