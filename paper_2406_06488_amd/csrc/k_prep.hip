@@ -44,12 +44,17 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
     mx = fmaxf(mx, fabsf(v[r]));  // fmaxf drops NaN; an Inf makes the scale 1 (flagged anyway)
   }
   if (ok) d.colpart[(int64_t)rc * d.p + k] = s;
-  if (d.prec == PREC_F32) {
+  if (d.prec == PREC_F32) {  // uniform per workgroup: one atomic per workgroup
+    __shared__ float wmax[4];
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
-    // non-negative floats order like their bit patterns
-    if ((threadIdx.x & 63) == 0 && mx > 0.0f)
-      atomicMax((unsigned int*)&d.flags[FLAG_XMAX], __float_as_uint(mx));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      mx = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+      // non-negative floats order like their bit patterns
+      if (mx > 0.0f) atomicMax((unsigned int*)&d.flags[FLAG_XMAX], __float_as_uint(mx));
+    }
   }
 }
 
