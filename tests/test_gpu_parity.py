@@ -62,6 +62,31 @@ def test_blocks_against_direct_differences(prec, kind):
     assert np.all(np.diag(dyy.double().cpu().numpy()) == diag)
 
 
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+def test_fp32_form_wide_dynamic_range(kind):
+    """The FP32 form stages each centred value as an fp16 pair scaled by a power of two set by
+    the test's largest |x|: columns spanning six decades and a large common offset must still
+    give FP32-accurate blocks and statistics."""
+    nx, ny, p = 170, 150, 40
+    g = np.random.Generator(np.random.PCG64(77))
+    scales = np.logspace(-3, 3, p)
+    X = g.standard_normal((nx, p)) * scales + 50.0
+    Y = g.standard_normal((ny, p)) * scales * 1.05 + 50.0
+    X, Y = X.astype(np.float32), Y.astype(np.float32)
+    gamma = 1.0 / float(np.sum(scales ** 2))
+    say("wide range", kind, nx, ny, p)
+    dxx, dyy, dxy = api.blocks(_dev(X, "f32"), _dev(Y, "f32"), kind, "f32", gamma)
+    torch.cuda.synchronize()
+    oxx, oyy, oxy = oracle.blocks(X.astype(np.float64), Y.astype(np.float64), KIND[kind], gamma)
+    for gm, o in ((dxx, oxx), (dyy, oyy), (dxy, oxy)):
+        gm = gm.double().cpu().numpy()
+        assert np.abs(gm - o).max() <= 3e-6 * np.abs(o).max(), (kind, np.abs(gm - o).max())
+    r = api.run(_dev(X, "f32"), _dev(Y, "f32"), 300, 4, kind, "f32", gamma)
+    torch.cuda.synchronize()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), 300, 4, KIND[kind], gamma)
+    compare_run(r, o, "f32", "wide range " + kind)
+
+
 # --------------------------------------------------------------------------- whole test
 
 CASES = [
