@@ -44,7 +44,7 @@ CASES = [
     (7, 1, 2, 40, 6, 8, 0.5),
     (1, 1, 4, 20, 7, 9, 1.0),            # only two distinct splits: exact ties
     (40, 33, 1, 300, 8, 10, 0.2),        # p = 1
-    (200, 160, 1030, 100, 9, 11, 0.1),   # FP32 Gram split over K
+    (200, 160, 1030, 100, 9, 11, 0.1),   # p above 1024: 33 K slices of 32 in the FP32 Gram
 ]
 
 

@@ -98,7 +98,7 @@ CASES = [
     (7, 1, 2, 40, 6, 8, 0.5),
     (1, 1, 4, 20, 7, 9, 1.0),
     (40, 33, 1, 300, 8, 10, 0.2),        # p = 1
-    (300, 170, 1030, 400, 9, 11, 0.1),   # FP32: Gram split over K (17 + 16 slices)
+    (300, 170, 1030, 400, 9, 11, 0.1),   # p above 1024: 33 K slices of 32 in the FP32 Gram
 ]
 
 
