@@ -142,13 +142,14 @@ def roofline(stage_ms, tests, prec, workload=None, gram_tests=None):
     return r, gram_tf, res_tf
 
 
-KERNEL_SOURCES = {"k_gram_f16x3": ["k_gram.hip", "common.h"],
-                  "k_gram_bf16": ["k_gram.hip", "common.h"],
-                  "k_dist_f64": ["k_gram.hip", "common.h"],
-                  "k_perm_mfma": ["k_perm.hip", "common.h"],
-                  "k_perm_f64": ["k_perm.hip", "common.h"],
-                  "k_precomp": ["k_baseline.hip", "common.h"],
-                  "k_hsic_terms": ["k_hsic.hip", "common.h"]}
+# a kernel's traffic depends on its source and on the launch shape the runtime picks
+KERNEL_SOURCES = {"k_gram_f16x3": ["k_gram.hip", "common.h", "runtime.cpp"],
+                  "k_gram_bf16": ["k_gram.hip", "common.h", "runtime.cpp"],
+                  "k_dist_f64": ["k_gram.hip", "common.h", "runtime.cpp"],
+                  "k_perm_mfma": ["k_perm.hip", "common.h", "runtime.cpp"],
+                  "k_perm_f64": ["k_perm.hip", "common.h", "runtime.cpp"],
+                  "k_precomp": ["k_baseline.hip", "common.h", "runtime.cpp"],
+                  "k_hsic_terms": ["k_hsic.hip", "common.h", "runtime.cpp"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
 
 
