@@ -96,9 +96,9 @@ static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
   // the FP64 kernel runs PC_STRIPS workgroups per row unit and may go down to one tile each
   const bool f64 = r.prec == ETEST_PREC_F64;
   const int64_t strips = f64 ? PC_STRIPS : 1;
-  // BF16-refined tests of 64 tiles or more: longer row units (measured on 5000 + 4000
-  // pooled rows: 5% less resampling time than 16 tiles per unit)
-  *kc = (r.prec == ETEST_PREC_BF16_REFINED && nt >= 64) ? 64 : 16;
+  // MFMA forms on 64 tiles or more: longer row units (measured on 5000 + 4000 pooled rows:
+  // 5% (BF16-refined) and 9% (FP32) less resampling time than 16 tiles per unit)
+  *kc = (!f64 && nt >= 64) ? 64 : 16;
   while (*kc > (f64 ? 1 : 2)) {
     int64_t nrk = 0;
     for (int64_t i = 0; i < nt; ++i) nrk += (nt - i + *kc - 1) / *kc;
