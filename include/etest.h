@@ -59,7 +59,11 @@ extern "C" {
 typedef enum {
   ETEST_OK = 0,
   ETEST_EINVAL = 1,      /* nx < 1, ny < 1, p < 1, B < 0 or B >= 2^31 - 1, NULL pointer, gamma <= 0 or
-                            non-finite, nx + ny > 2^31 - 1, bad request field        */
+                            non-finite, nx + ny > 2^31 - 1, bad request field; a pooled
+                            tile grid ceil(nx/128) + ceil(ny/128) above 46340 tiles; a
+                            stage launch past one dispatch (2^31 workgroups or 2^32
+                            work-items, e.g. one workgroup per stored 128 x 128 block
+                            tile: nt (nt + 1) / 2 < 2^24), checked before any device work */
   ETEST_ENONFINITE = 2,  /* X or Y holds a NaN or an Inf                                 */
   ETEST_ENOMEM = 3,      /* device memory, or the server's memory budget, exhausted      */
   ETEST_EDEVICE = 4,     /* a HIP runtime call failed                                    */

@@ -41,6 +41,16 @@ constexpr int HSIC_NMAX = 4096;      // HSIC test: largest n (one sort and one k
 constexpr int HSIC_RB = 8;           // HSIC test: rows of Kt per workgroup of the term pass
 constexpr int PC_ROWS = 32;          // pre-computation test: tile rows per strip
 constexpr int PC_STRIPS = TILE / PC_ROWS;
+// Threads per workgroup of the kernels whose launch sizes the host checks.
+constexpr int CM_GROUPS = 16;        // column-mean pass: 64-thread groups per workgroup
+constexpr int MTHREADS = 320;        // split stream: wave 0 scans, waves 1..4 draw
+constexpr int PERM_THREADS = 512;    // MFMA resampling: 8 waves
+constexpr int PS_GROUPS = 16;        // split statistics: 64-thread groups per workgroup
+// Largest pooled tile grid of one test (tx + ty tiles, nx and ny each padded to whole
+// tiles): for nt <= 46340 the stored tile count nt (nt + 1) / 2 and every intermediate of
+// the triangular tile index (i * nt) stay below 2^31.  That is 5.9 million pooled rows,
+// whose blocks (~70 TB) no single GPU holds; requests beyond it are rejected as invalid.
+constexpr int64_t MAX_TILE_GRID = 46340;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
 enum { KIND_ED = 0, KIND_MMD = 1 };
@@ -153,9 +163,11 @@ __device__ inline int find_test(const int64_t* __restrict__ offs, int ntests, in
   return lo;
 }
 
-// Stored upper tile index of (i, j), i <= j, in an nt x nt tile grid.
-__host__ __device__ inline int tile_index(int i, int j, int nt) {
-  return i * nt - (i * (i - 1)) / 2 + (j - i);
+// Stored upper tile index of (i, j), i <= j, in an nt x nt tile grid (formed in 64 bits;
+// below 2^31 whenever nt <= MAX_TILE_GRID).
+__host__ __device__ inline int64_t tile_index(int i, int j, int nt) {
+  const int64_t a = i;
+  return a * nt - (a * (a - 1)) / 2 + (j - i);
 }
 
 // Inverse of tile_index.

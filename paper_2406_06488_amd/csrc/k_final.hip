@@ -15,7 +15,6 @@ namespace et {
 // threshold bit for bit as the column's own workgroup computes it.  Exceedances are
 // counted with one integer atomic per workgroup; the last workgroup of a test writes the
 // result.
-constexpr int PS_GROUPS = 16;
 
 __device__ inline double split_statistic(const TestDesc& d, double q) {
   if (d.prec != PREC_F64) q /= d.obs[5];  // undo the power-of-two scale of the fp16 planes

@@ -62,7 +62,6 @@ struct SplitDraw {
 // lane per split) over the current one.  Positions without an item (tile padding)
 // hold v = 0xFFFFFFFF, which is never below need (< 2^31), so the scan is the same
 // branch-free step for every position and writes whole words.
-constexpr int MTHREADS = 320;  // wave 0 scans, waves 1..4 draw
 constexpr int MSPL = MEMBER_SPLITS;
 
 __device__ inline uint32_t scaled_draw(uint32_t lo, uint32_t hi, uint32_t m) {

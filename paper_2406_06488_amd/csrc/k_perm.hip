@@ -81,7 +81,6 @@ __device__ inline PermUnit perm_unit(const TestDesc& d, int ti, int64_t local,
 // fragment order -- and the membership words of column tile j stream straight into one
 // of two LDS buffers (global_load_lds) while the other buffer is multiplied.  Each wave
 // folds the row weights of its own columns at the end: no cross-wave reduction.
-constexpr int PERM_THREADS = 512;
 
 __device__ inline void load_to_lds16(const void* g, void* lds_wave_base) {
   __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave_base, 16,

@@ -60,7 +60,6 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
 
 // Column means: 64 columns per workgroup, 16 groups of waves each summing every 16th
 // partial, then the 16 group sums in order (a fixed order: the result is reproducible).
-constexpr int CM_GROUPS = 16;
 __global__ void __launch_bounds__(64 * CM_GROUPS) k_colmean(const TestDesc* __restrict__ descs,
                                                             const int64_t* __restrict__ offs,
                                                             int ntests) {

@@ -47,6 +47,12 @@ etest_status validate_request(const etest_request& r) {
   if (r.p < 1) return set_error(ETEST_EINVAL, "p must be >= 1");
   if (r.B < 0) return set_error(ETEST_EINVAL, "B must be >= 0");
   if (r.nx + r.ny > 2147483647LL) return set_error(ETEST_EINVAL, "nx + ny must be < 2^31");
+  // ny = 0 only for the one-sample plans of the HSIC test (never a two-sample request)
+  const int64_t nt = (r.nx + TILE - 1) / TILE + (r.ny + TILE - 1) / TILE;
+  if (nt > MAX_TILE_GRID)
+    return set_error(ETEST_EINVAL, "nx + ny too large for one test: " + std::to_string(nt) +
+                                       " pooled tiles of 128 rows, at most " +
+                                       std::to_string(MAX_TILE_GRID));
   if (r.p > 2147483647LL / 2) return set_error(ETEST_EINVAL, "p too large");
   if (r.B > 2147483646LL) return set_error(ETEST_EINVAL, "B must be < 2^31 - 1");
   if (r.kind == ETEST_MMD && !(std::isfinite(r.gamma) && r.gamma > 0.0))
@@ -120,7 +126,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   d.tx = (int32_t)((r.nx + TILE - 1) / TILE);
   d.ty = (int32_t)((r.ny + TILE - 1) / TILE);
   d.nt = d.tx + d.ty;
-  d.ntiles = d.nt * (d.nt + 1) / 2;
+  // below 2^31 for every grid validate_request accepts (nt <= MAX_TILE_GRID)
+  d.ntiles = (int32_t)((int64_t)d.nt * (d.nt + 1) / 2);
   // fp16 planes of the centred blocks: hi + lo 2^-11 keeps ~22 significant bits of each
   // centred entry.  One plane (11 bits) is not enough even for the BF16 form: a statistic
   // is a sum with heavy cancellation, and on small tests 11-bit entries move it by ~1e-3.
@@ -130,9 +137,12 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   int32_t kc_t, cc_t;
   tuned_shape(r, &kc_t, &cc_t);
   d.kc = (int32_t)(kc_override > 0 ? kc_override : kc_t);
-  int nrk = 0;
-  for (int i = 0; i < d.nt; ++i) nrk += (d.nt - i + d.kc - 1) / d.kc;
-  d.n_rowk = r.prec == ETEST_PREC_F64 ? nrk * PC_STRIPS : nrk;  // FP64: one unit per strip
+  int64_t nrk = 0;
+  for (int64_t i = 0; i < d.nt; ++i) nrk += (d.nt - i + d.kc - 1) / d.kc;
+  if (r.prec == ETEST_PREC_F64) nrk *= PC_STRIPS;  // FP64: one unit per strip
+  // a count past 2^31 - 1 (tiny row units on a huge grid) is saturated here and rejected by
+  // check_launch_sizes
+  d.n_rowk = (int32_t)std::min<int64_t>(nrk, 2147483647LL);
   const int64_t n = r.nx + r.ny;
   d.nrowchunks = (int32_t)((n + COLSUM_ROWS - 1) / COLSUM_ROWS);
   d.B = r.B;
@@ -254,6 +264,38 @@ void link_partners(TestDesc* descs, const Pairing& pairing) {
   }
 }
 
+// Threads per workgroup of each launch slot.
+static int slot_threads(int s) {
+  switch (s) {
+    case S_COLMEAN: return 64 * CM_GROUPS;
+    case S_MEMBER: return MTHREADS;
+    case S_ROWSUM: return 64;
+    case S_PERM_S2:
+    case S_PERM_S3: return PERM_THREADS;
+    case S_PSTAT: return 64 * PS_GROUPS;
+    default: return 256;
+  }
+}
+
+// Every launch of a batch is one flattened grid per slot: its workgroup count must stay
+// below 2^31 (workgroup indices are formed in 32 bits) and its work-item count below 2^32
+// (the dispatch's grid size); a test's row units must stay below 2^31 as well.
+etest_status check_launch_sizes(const std::vector<TestPlan>& plans) {
+  for (const TestPlan& P : plans)
+    if (P.d.n_rowk >= 2147483647) return set_error(ETEST_EINVAL, "too many resampling row units");
+  for (int s = 0; s < S_COUNT; ++s) {
+    int64_t total = 0;
+    for (const TestPlan& P : plans) {
+      total += P.wg[s];
+      if (total > 2147483647LL || total * slot_threads(s) > 4294967295LL)
+        return set_error(ETEST_EINVAL, "launch of slot " + std::to_string(s) + " too large (" +
+                                           std::to_string(total) +
+                                           "+ workgroups): fewer splits or fewer tests per call");
+    }
+  }
+  return ETEST_OK;
+}
+
 etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_perm, Batch* b) {
   b->plans.clear();
   b->plans.reserve((size_t)n);
@@ -281,7 +323,7 @@ etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_per
       b->plans[(size_t)u].wg[k] = 0;
     if (pairing.share_z[(size_t)s]) b->plans[(size_t)u].wg[S_MEMBER] = 0;
   }
-  return ETEST_OK;
+  return check_launch_sizes(b->plans);
 }
 
 void assign_pointers(TestPlan& P, char* r, DevResult* result) {

@@ -81,6 +81,8 @@ struct TestPlan {
 // Sets the calling thread's error message; returns the status.
 etest_status set_error(etest_status s, const std::string& msg);
 etest_status validate_request(const etest_request& r);
+// EINVAL when a launch of the plans would exceed what one dispatch can address.
+etest_status check_launch_sizes(const std::vector<TestPlan>& plans);
 // Plan modes: the efficient test; blocks and observed statistic only (one recomputation of
 // the standard test); pooled blocks, split stream and the pre-computation test's buffers.
 enum PlanMode { PLAN_EFFICIENT = 0, PLAN_BLOCKS = 1, PLAN_PRECOMP = 2 };

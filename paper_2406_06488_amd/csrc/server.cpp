@@ -194,6 +194,11 @@ extern "C" etest_status etest_server_submit(etest_server* S, const etest_request
   Req* q = new Req();
   q->r = *req;
   q->plan = make_plan(*req);
+  s = check_launch_sizes({q->plan});
+  if (s != ETEST_OK) {
+    delete q;
+    return s;
+  }
   q->footprint = (int64_t)q->plan.bytes;
   q->pc_total = (int)(q->plan.d.B_pad / NP);
   if (q->footprint > S->cfg.memory_budget_bytes) {

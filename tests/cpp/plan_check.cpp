@@ -160,8 +160,85 @@ static void check_row_units() {
     }
 }
 
+// Requests at and past the largest tile grid: the planner's tile counts and footprints are
+// formed in 64 bits and never wrap; grids past MAX_TILE_GRID and launches past what one
+// dispatch addresses are rejected as invalid (nothing here touches a device).
+static void check_large_grids() {
+  auto req = [](int64_t nx, int64_t ny, int64_t p, int64_t B, int prec) {
+    etest_request r{};
+    r.kind = ETEST_ED;
+    r.prec = prec;
+    r.nx = nx;
+    r.ny = ny;
+    r.p = p;
+    r.B = B;
+    r.seed = 1;
+    r.X = (const void*)0x1000;
+    r.Y = (const void*)0x2000;
+    return r;
+  };
+  const int64_t T = TILE;
+  // nt = 46340 (accepted), 46341, 65536 and n = 2^31 - 1 (rejected), at p = 1
+  {
+    const etest_request r = req(23170 * T, 23170 * T, 1, 100, ETEST_PREC_F32);
+    CHECK(validate_request(r) == ETEST_OK, "nt = 46340 rejected");
+    const TestPlan P = make_plan(r);
+    const int64_t nt = 46340, ntiles = nt * (nt + 1) / 2;
+    CHECK(P.d.nt == nt && P.d.ntiles == ntiles, "ntiles %lld != %lld", (long long)P.d.ntiles,
+          (long long)ntiles);
+    CHECK(P.size[B_D] == (size_t)ntiles * T * T * 4, "D bytes %zu", P.size[B_D]);
+    CHECK(P.bytes > (size_t)ntiles * T * T * 8, "footprint %zu wrapped", P.bytes);
+    int64_t fp = 0;
+    CHECK(etest_footprint(&r, &fp) == ETEST_OK && fp > (int64_t)70e12, "footprint %lld",
+          (long long)fp);
+    // the last stored tile's index and the middle row's first tile, formed in 64 bits
+    CHECK(tile_index((int)nt - 1, (int)nt - 1, (int)nt) == ntiles - 1, "last tile index");
+    const int64_t i = nt / 2;
+    CHECK(tile_index((int)i, (int)i, (int)nt) == i * nt - i * (i - 1) / 2, "middle tile index");
+    // its Gram launch (one workgroup per stored tile) exceeds one dispatch's 2^32 work-items
+    Batch b;
+    CHECK(build_batch(&r, 1, false, &b) == ETEST_EINVAL, "nt = 46340 batch accepted");
+  }
+  // the largest grids whose launches fit: every slot's grid below 2^31 workgroups and 2^32
+  // work-items (the Gram's 256-thread workgroups allow nt(nt+1)/2 < 2^24)
+  for (const int64_t nt : {(int64_t)2000, (int64_t)5791}) {
+    const etest_request r = req(nt / 2 * T, (nt - nt / 2) * T, 1, 1000, ETEST_PREC_F32);
+    Batch b;
+    CHECK(build_batch(&r, 1, false, &b) == ETEST_OK, "nt = %lld rejected: %s", (long long)nt,
+          etest_last_error());
+    if (!b.plans.empty())
+      CHECK(b.plans[0].wg[S_GRAM_F32] == nt * (nt + 1) / 2, "gram grid of nt = %lld",
+            (long long)nt);
+  }
+  for (const int64_t n : {(int64_t)46341 * T, (int64_t)65536 * T, (int64_t)2147483647})
+    for (int prec : {ETEST_PREC_F64, ETEST_PREC_F32, ETEST_PREC_BF16_REFINED}) {
+      const etest_request r = req(n / 2, n - n / 2, 1, 10, prec);
+      CHECK(validate_request(r) == ETEST_EINVAL, "n = %lld accepted", (long long)n);
+      int64_t fp = -7;
+      CHECK(etest_footprint(&r, &fp) == ETEST_EINVAL && fp == -7, "footprint of n = %lld",
+            (long long)n);
+      Batch b;
+      CHECK(build_batch(&r, 1, false, &b) == ETEST_EINVAL, "batch of n = %lld", (long long)n);
+    }
+  // a valid grid whose resampling launch exceeds one dispatch (2^32 work-items): EINVAL
+  {
+    const etest_request r = req(20000, 20000, 10, 2000000000, ETEST_PREC_BF16_REFINED);
+    CHECK(validate_request(r) == ETEST_OK, "large-B request rejected by validation");
+    Batch b;
+    CHECK(build_batch(&r, 1, false, &b) == ETEST_EINVAL, "oversized resampling launch accepted");
+  }
+  // tuned row units of one tile on a large FP64 grid: row-unit count past 2^31 is rejected
+  {
+    const etest_request r = req(20000 * T, 20000 * T, 1, 0, ETEST_PREC_F64);
+    const TestPlan P = make_plan(r, 1);
+    CHECK(P.d.n_rowk == 2147483647, "n_rowk not saturated: %d", P.d.n_rowk);
+    CHECK(check_launch_sizes({P}) == ETEST_EINVAL, "saturated row units accepted");
+  }
+}
+
 int main() {
   check_row_units();
+  check_large_grids();
   const int precs[3] = {ETEST_PREC_F64, ETEST_PREC_F32, ETEST_PREC_BF16_REFINED};
   const int64_t shapes[][4] = {{1, 1, 1, 0},       {1, 5, 3, 40},       {100, 100, 10, 1000},
                                {129, 127, 64, 255}, {2000, 2000, 1000, 10000},
