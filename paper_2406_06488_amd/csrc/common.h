@@ -53,6 +53,26 @@ constexpr int PS_GROUPS = 16;        // split statistics: 64-thread groups per w
 constexpr int64_t MAX_TILE_GRID = 46340;
 
 enum { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16R = 2 };
+// Operand format of the Gram (and of the staged rows it reads): FP64 rows (direct
+// differences), fp16 pairs (hi, lo) of the scaled centred value (FP32-accurate products),
+// or BF16 values.  The FP32 form uses fp16 pairs; the BF16-refined form uses BF16 operands
+// from BF16_PAIR_MAX_P coordinates on and fp16 pairs below, where 8-bit coordinates move a
+// distance by ~2^-9 / sqrt(p) of itself (beyond the form's 1e-3 statistic bound at p = 10)
+// and the Gram is a negligible share of the test.
+enum { GOP_F64 = 0, GOP_F16PAIR = 1, GOP_BF16 = 2 };
+constexpr int BF16_PAIR_MAX_P = 64;
+__host__ __device__ inline int gram_operands(int prec, int64_t p) {
+  return prec == PREC_F64 ? GOP_F64
+         : (prec == PREC_F32 || p < BF16_PAIR_MAX_P) ? GOP_F16PAIR : GOP_BF16;
+}
+// K-slice width of each Gram kernel: staged rows are padded to a multiple of it.
+__host__ __device__ inline int gram_k_slice(int gop) {
+  return gop == GOP_F64 ? 16 : (gop == GOP_F16PAIR ? 32 : 64);
+}
+// Bytes per staged operand element: FP64, one fp16 pair, one BF16 value.
+__host__ __device__ inline int gram_operand_bytes(int gop) {
+  return gop == GOP_F64 ? 8 : (gop == GOP_F16PAIR ? 4 : 2);
+}
 enum { KIND_ED = 0, KIND_MMD = 1 };
 
 // Result written by the device (the public etest_result plus a status word).
@@ -74,6 +94,7 @@ __host__ __device__ inline int plane_bytes_per_entry(int pfmt) {
 
 struct TestDesc {
   int32_t kind, prec, pfmt, refine;  // pfmt: plane format of the centred tiles (PLANES_*)
+  int32_t gop, gop_pad;              // gop: operand format of the Gram (GOP_*)
   int32_t nx, ny, p, p_pad;
   int32_t tx, ty, nt, ntiles;
   int32_t kc, n_rowk, nrowchunks, cc;  // cc: split-column chunks per resampling workgroup

@@ -276,7 +276,7 @@ __device__ inline void gram_epilogue(const TestDesc& d, const TileCtx& c, f32x16
   add_refined(d, refined);
 }
 
-// ---------------------------------------------------------------- FP32 form on fp16 MFMA
+// ------------------------------------------- fp16-pair operands (FP32-accurate) on fp16 MFMA
 // The staged operand holds fp16 pairs (hi, lo) of w 2^e (22 significant bits; see
 // f16_split_exponent).  Each Gram entry is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b
 // (the lo_a lo_b term, 2^-22 of the product, is dropped) with three
@@ -566,15 +566,15 @@ __global__ void __launch_bounds__(256) k_dist_f64(const TestDesc* __restrict__ d
   }
 }
 
-void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d,
+void launch_gram(int gop, int64_t blocks, hipStream_t st, const TestDesc* d,
                  const int64_t* offs, int n, bool dual) {
   if (blocks <= 0) return;
   const dim3 g((unsigned)blocks), b(256);
-  if (prec == PREC_F64)
+  if (gop == GOP_F64)
     hipLaunchKernelGGL(k_dist_f64, g, b, 0, st, d, offs, n);
-  else if (prec == PREC_F32 && dual)
+  else if (gop == GOP_F16PAIR && dual)
     hipLaunchKernelGGL(k_gram_f16x3<true>, g, b, 0, st, d, offs, n);
-  else if (prec == PREC_F32)
+  else if (gop == GOP_F16PAIR)
     hipLaunchKernelGGL(k_gram_f16x3<false>, g, b, 0, st, d, offs, n);
   else if (dual)
     hipLaunchKernelGGL(k_gram_bf16<true>, g, b, 0, st, d, offs, n);

@@ -19,9 +19,9 @@ __device__ inline double load_in_f64(const TestDesc& d, int64_t t, int k) {
 }
 
 // Partial column sums over chunks of ROWCHUNK pooled rows (FP64).  All ROWCHUNK loads of a
-// thread are issued before the (fixed-order) sum, so they are in flight together.  The FP32
-// form also takes max |x| over the input (one atomic per wave), which sets the scale of its
-// fp16 operand pairs.
+// thread are issued before the (fixed-order) sum, so they are in flight together.  Tests
+// whose Gram reads fp16 pairs also take max |x| over the input (one atomic per workgroup),
+// which sets the scale of those pairs.
 __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ descs,
                                                  const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
     mx = fmaxf(mx, fabsf(v[r]));  // fmaxf drops NaN; an Inf makes the scale 1 (flagged anyway)
   }
   if (ok) d.colpart[(int64_t)rc * d.p + k] = s;
-  if (d.prec == PREC_F32) {  // uniform per workgroup: one atomic per workgroup
+  if (d.gop == GOP_F16PAIR) {  // uniform per workgroup: one atomic per workgroup
     __shared__ float wmax[4];
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
@@ -85,7 +85,7 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// FP32 form: w -> (hi, lo) with hi = fp16(w 2^e), lo = fp16(w 2^e - hi), packed hi in the
+// fp16-pair operands: w -> (hi, lo) with hi = fp16(w 2^e), lo = fp16(w 2^e - hi), packed hi in the
 // low half; *r = (hi + lo) 2^-e, the value the Gram's products see (its norm goes to nrm, so
 // that |a|^2 + |b|^2 - 2 g is formed from one set of operand values).
 __device__ inline uint32_t f16_pair(float w, int e, double* r) {
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
   }
   bool bad = false;
   double nrm = 0.0;
-  if (d.prec == PREC_F64) {
+  if (d.gop == GOP_F64) {
     double* W = (double*)d.W + pos * d.p_pad;
     for (int k = lane; k < d.p_pad; k += 64) {
       double v = 0.0;
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
     nrm = wave_sum(nrm);
     if (lane == 0) ((double*)d.nrm)[pos] = nrm;
   } else {
-    const bool bf = d.prec == PREC_BF16R;
+    const bool bf = d.gop == GOP_BF16;
     const int e = bf ? 0 : f16_split_exponent(d);
     const float* src = t < 0 ? nullptr : pooled_row<float>(d, t);
     // four columns per lane when every row starts on a 16-byte boundary

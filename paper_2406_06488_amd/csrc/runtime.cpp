@@ -121,7 +121,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   d.nx = (int32_t)r.nx;
   d.ny = (int32_t)r.ny;
   d.p = (int32_t)r.p;
-  const int kq = r.prec == ETEST_PREC_F64 ? 16 : (r.prec == ETEST_PREC_F32 ? 32 : 64);
+  d.gop = gram_operands(r.prec, r.p);
+  const int kq = gram_k_slice(d.gop);
   d.p_pad = (int32_t)((r.p + kq - 1) / kq * kq);
   d.tx = (int32_t)((r.nx + TILE - 1) / TILE);
   d.ty = (int32_t)((r.ny + TILE - 1) / TILE);
@@ -159,7 +160,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
 
   const bool f64 = r.prec == ETEST_PREC_F64;
   const int64_t npad = (int64_t)d.nt * TILE;
-  const size_t el_w = f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2);
+  const size_t el_w = (size_t)gram_operand_bytes(d.gop);
   const size_t el_d = f64 ? 8 : 4;
   size_t sz[B_NBUF] = {};
   sz[B_COLPART] = f64 ? 0 : (size_t)d.nrowchunks * r.p * 8;
@@ -203,8 +204,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   P.wg[S_COLMEAN] = f32like ? (r.p + 63) / 64 : 0;
   P.wg[S_STAGE] = npad / 4;
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
-  P.wg[S_GRAM_F32] = r.prec == ETEST_PREC_F32 ? d.ntiles : 0;
-  P.wg[S_GRAM_BF16] = r.prec == ETEST_PREC_BF16_REFINED ? d.ntiles : 0;
+  P.wg[S_GRAM_F32] = d.gop == GOP_F16PAIR ? d.ntiles : 0;
+  P.wg[S_GRAM_BF16] = d.gop == GOP_BF16 ? d.ntiles : 0;
   P.wg[S_MEMBER] = d.B_pad / MEMBER_SPLITS;
   P.wg[S_ROWSUM] = (2 * npad + 63) / 64;  // two threads per pooled position
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
@@ -280,13 +281,14 @@ static int slot_threads(int s) {
 // Every launch of a batch is one flattened grid per slot: its workgroup count must stay
 // below 2^31 (workgroup indices are formed in 32 bits) and its work-item count below 2^32
 // (the dispatch's grid size); a test's row units must stay below 2^31 as well.
-etest_status check_launch_sizes(const std::vector<TestPlan>& plans) {
-  for (const TestPlan& P : plans)
-    if (P.d.n_rowk >= 2147483647) return set_error(ETEST_EINVAL, "too many resampling row units");
+etest_status check_launch_sizes(const TestPlan* plans, size_t n) {
+  for (size_t t = 0; t < n; ++t)
+    if (plans[t].d.n_rowk >= 2147483647)
+      return set_error(ETEST_EINVAL, "too many resampling row units");
   for (int s = 0; s < S_COUNT; ++s) {
     int64_t total = 0;
-    for (const TestPlan& P : plans) {
-      total += P.wg[s];
+    for (size_t t = 0; t < n; ++t) {
+      total += plans[t].wg[s];
       if (total > 2147483647LL || total * slot_threads(s) > 4294967295LL)
         return set_error(ETEST_EINVAL, "launch of slot " + std::to_string(s) + " too large (" +
                                            std::to_string(total) +
@@ -323,7 +325,7 @@ etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_per
       b->plans[(size_t)u].wg[k] = 0;
     if (pairing.share_z[(size_t)s]) b->plans[(size_t)u].wg[S_MEMBER] = 0;
   }
-  return check_launch_sizes(b->plans);
+  return check_launch_sizes(b->plans.data(), b->plans.size());
 }
 
 void assign_pointers(TestPlan& P, char* r, DevResult* result) {
@@ -406,18 +408,17 @@ void free_batch(Batch* b, hipStream_t st, bool stream_ordered) {
   b->ws = nullptr;
 }
 
-void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
-                   const StageEvents* ev, const Fork* fork) {
-  const int n = (int)b.plans.size();
-  auto offs = [&](Slot s) { return b.d_offs + (size_t)s * (n + 1); };
-  auto total = [&](Slot s) { return b.offs[(size_t)s * (n + 1) + n]; };
+void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_offs, int n,
+                    bool dual, hipStream_t st, const uint32_t* import_words, int64_t import_bpad,
+                    const StageEvents* ev, const Fork* fork) {
+  auto offs = [&](Slot s) { return d_offs + (size_t)s * (n + 1); };
+  auto total = [&](Slot s) { return h_offs[(size_t)s * (n + 1) + n]; };
   auto begin = [&](int k, hipStream_t s) {
     if (ev && (ev->mask >> k & 1u)) (void)hipEventRecord(ev->begin[k], s);
   };
   auto end = [&](int k, hipStream_t s) {
     if (ev && (ev->mask >> k & 1u)) (void)hipEventRecord(ev->end[k], s);
   };
-  const TestDesc* D = b.d_descs;
   launch_clear_flags(st, D, nullptr, n);
   begin(0, st);
   launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), n);
@@ -433,16 +434,14 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
     ms = fork->aux;
   }
   begin(2, ms);
-  if (import_words) launch_member_import(b.plans[0].d.B_pad, ms, D, import_words);
+  if (import_words) launch_member_import(import_bpad, ms, D, import_words);
   else launch_member(total(S_MEMBER), ms, D, offs(S_MEMBER), n);
   end(2, ms);
   if (fork) (void)hipEventRecord(fork->done, ms);
   begin(1, st);
-  bool dual = false;
-  for (const TestPlan& P : b.plans) dual = dual || P.partner >= 0;
-  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n, dual);
-  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n, dual);
-  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n, dual);
+  launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n, dual);
+  launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n, dual);
+  launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n, dual);
   end(1, st);
   begin(3, st);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), n);
@@ -461,6 +460,14 @@ void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
   begin(6, st);
   launch_pstat(total(S_PSTAT), st, D, offs(S_PSTAT), n);
   end(6, st);
+}
+
+void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words,
+                   const StageEvents* ev, const Fork* fork) {
+  bool dual = false;
+  for (const TestPlan& P : b.plans) dual = dual || P.partner >= 0;
+  enqueue_stages(b.d_descs, b.d_offs, b.offs.data(), (int)b.plans.size(), dual, st, import_words,
+                 import_words ? b.plans[0].d.B_pad : 0, ev, fork);
 }
 
 // Fork/join and stage events only order work on this device (and time it): they skip the
@@ -1013,7 +1020,8 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
   d.ny = (int32_t)(r.nx + r.ny - nx1 - ny1);  // y side
   d.p = (int32_t)r.p;
   const bool f64 = r.prec == ETEST_PREC_F64;
-  const int kq = f64 ? 16 : (r.prec == ETEST_PREC_F32 ? 32 : 64);
+  d.gop = gram_operands(r.prec, r.p);
+  const int kq = gram_k_slice(d.gop);
   d.p_pad = (int32_t)((r.p + kq - 1) / kq * kq);
   d.tx = (d.nx + TILE - 1) / TILE;
   d.ty = (d.ny + TILE - 1) / TILE;
@@ -1025,7 +1033,7 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
   d.X = r.X;
   d.Y = r.Y;
   const int64_t npad = (int64_t)d.nt * TILE;
-  const size_t el_w = f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2);
+  const size_t el_w = (size_t)gram_operand_bytes(d.gop);
   // workspace: descriptor, launch tables, then the buffers the stages index
   enum { C_DESC, C_OFFS, C_COLPART, C_COLMEAN, C_W, C_NRM, C_TSUM, C_TMAX, C_V, C_OBS, C_FLAGS, C_N };
   size_t sz[C_N];
@@ -1087,8 +1095,7 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
     launch_stage(wg[2], st, D, O + 4, 1);
     mark(0, false);
     mark(1, true);
-    launch_gram(f64 ? PREC_F64 : (r.prec == ETEST_PREC_F32 ? PREC_F32 : PREC_BF16R), wg[3], st, D,
-                O + 6, 1, false);
+    launch_gram(d.gop, wg[3], st, D, O + 6, 1, false);
     mark(1, false);
     mark(6, true);
     launch_cross_final(st, D);
@@ -1129,9 +1136,9 @@ static void enqueue_blocks(const Batch& b, int m, hipStream_t st) {
   launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), m);
   launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), m);
   launch_stage(total(S_STAGE), st, D, offs(S_STAGE), m);
-  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), m, false);
-  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), m, false);
-  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), m, false);
+  launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), m, false);
+  launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), m, false);
+  launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), m, false);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), m);
   launch_observed(st, D, nullptr, m);
 }
@@ -1238,9 +1245,9 @@ static etest_status run_precomputed(const etest_request& r, hipStream_t st, etes
   launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), 1);
   mark(2, false);
   mark(1, true);
-  launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), 1, false);
-  launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), 1, false);
-  launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 1, false);
+  launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), 1, false);
+  launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), 1, false);
+  launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 1, false);
   mark(1, false);
   mark(5, true);
   launch_precomp(r.prec == ETEST_PREC_F64, D, d.ntiles, r.B, d.part, st);
@@ -1322,9 +1329,9 @@ static etest_status run_hsic(const etest_hsic_request& h, hipStream_t st, etest_
   launch_stage(tot(S_STAGE), st, D, offs(S_STAGE), 2);
   mark(0, false);
   mark(1, true);
-  launch_gram(PREC_F64, tot(S_GRAM_F64), st, D, offs(S_GRAM_F64), 2, false);
-  launch_gram(PREC_F32, tot(S_GRAM_F32), st, D, offs(S_GRAM_F32), 2, false);
-  launch_gram(PREC_BF16R, tot(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 2, false);
+  launch_gram(GOP_F64, tot(S_GRAM_F64), st, D, offs(S_GRAM_F64), 2, false);
+  launch_gram(GOP_F16PAIR, tot(S_GRAM_F32), st, D, offs(S_GRAM_F32), 2, false);
+  launch_gram(GOP_BF16, tot(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 2, false);
   mark(1, false);
   mark(2, true);
   launch_permgen(n, h.seed, 0, B, nperm, perms, st);

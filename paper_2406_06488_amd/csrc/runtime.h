@@ -16,7 +16,7 @@ void launch_colpart(int64_t blocks, hipStream_t st, const TestDesc* d, const int
 void launch_colmean(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_stage(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_cross_final(hipStream_t st, const TestDesc* d);
-void launch_gram(int prec, int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
+void launch_gram(int gop, int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
                  int n, bool dual = false);
 void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
@@ -82,7 +82,7 @@ struct TestPlan {
 etest_status set_error(etest_status s, const std::string& msg);
 etest_status validate_request(const etest_request& r);
 // EINVAL when a launch of the plans would exceed what one dispatch can address.
-etest_status check_launch_sizes(const std::vector<TestPlan>& plans);
+etest_status check_launch_sizes(const TestPlan* plans, size_t n);
 // Plan modes: the efficient test; blocks and observed statistic only (one recomputation of
 // the standard test); pooled blocks, split stream and the pre-computation test's buffers.
 enum PlanMode { PLAN_EFFICIENT = 0, PLAN_BLOCKS = 1, PLAN_PRECOMP = 2 };
@@ -102,6 +102,10 @@ struct Batch {
   std::vector<size_t> base;      // each test's region offset inside ws
 };
 
+// Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).
+etest_status scratch_region(void** ptr, size_t* bytes);
+void launch_put_desc(const TestDesc& d, const int64_t* offs, TestDesc* dd, int64_t* doffs,
+                     hipStream_t st);
 // Point a plan's descriptor at its buffers inside a device region.
 void assign_pointers(TestPlan& P, char* region, DevResult* result);
 // ED / MMD pairs of a request list that share staging and Gram: partner[s] = t when the
@@ -135,6 +139,13 @@ struct Fork {
   hipEvent_t start, done;
 };
 
+// Enqueue every stage of n tests whose descriptors (D) and launch tables (d_offs, with the
+// same tables on the host in h_offs: [S_COUNT][n + 1] prefix sums of workgroups) are in
+// device memory.  dual: some ED test also writes its MMD partner's blocks.  import_words:
+// caller splits for a single test of B_pad import_bpad (or null).
+void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_offs, int n,
+                    bool dual, hipStream_t st, const uint32_t* import_words, int64_t import_bpad,
+                    const StageEvents* ev, const Fork* fork);
 // Enqueue every stage.  import_words: caller splits for a single test (or null).
 void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words = nullptr,
                    const StageEvents* events = nullptr, const Fork* fork = nullptr);

@@ -194,7 +194,7 @@ extern "C" etest_status etest_server_submit(etest_server* S, const etest_request
   Req* q = new Req();
   q->r = *req;
   q->plan = make_plan(*req);
-  s = check_launch_sizes({q->plan});
+  s = check_launch_sizes(&q->plan, 1);
   if (s != ETEST_OK) {
     delete q;
     return s;
@@ -430,9 +430,9 @@ void run_scheduler(etest_server* S) {
         launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), R);
         launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), R);
         launch_stage(total(S_STAGE), st, D, offs(S_STAGE), R);
-        launch_gram(PREC_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), R);
-        launch_gram(PREC_F32, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), R);
-        launch_gram(PREC_BF16R, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), R);
+        launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), R);
+        launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), R);
+        launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), R);
         launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), R);
         launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), R);
         launch_observed(st, D, offs(SEL_FRONT), R);

@@ -61,7 +61,7 @@ static void check_plan(const etest_request& r, bool internal) {
   // what the kernels index, in bytes
   const bool f64 = r.prec == ETEST_PREC_F64;
   size_t need[B_NBUF] = {};
-  need[B_W] = (size_t)npad * d0.p_pad * (f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2));
+  need[B_W] = (size_t)npad * d0.p_pad * gram_operand_bytes(d0.gop);
   need[B_D] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 4);
   need[B_PLANES] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : plane_bytes_per_entry(d0.pfmt));
   need[B_Z] = (size_t)d0.nt * TILE_WORDS * d0.B_pad * 4;
@@ -106,7 +106,7 @@ static void check_mode_plan(const etest_request& r, int mode) {
   const int64_t npad = (int64_t)d0.nt * TILE;
   const bool f64 = r.prec == ETEST_PREC_F64;
   size_t need[B_NBUF] = {};
-  need[B_W] = (size_t)npad * d0.p_pad * (f64 ? 8 : (r.prec == ETEST_PREC_F32 ? 4 : 2));
+  need[B_W] = (size_t)npad * d0.p_pad * gram_operand_bytes(d0.gop);
   need[B_D] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 4);
   need[B_RSUM] = (size_t)npad * 16;
   need[B_TSUM] = (size_t)d0.ntiles * 2 * TILE * 8;
@@ -232,7 +232,7 @@ static void check_large_grids() {
     const etest_request r = req(20000 * T, 20000 * T, 1, 0, ETEST_PREC_F64);
     const TestPlan P = make_plan(r, 1);
     CHECK(P.d.n_rowk == 2147483647, "n_rowk not saturated: %d", P.d.n_rowk);
-    CHECK(check_launch_sizes({P}) == ETEST_EINVAL, "saturated row units accepted");
+    CHECK(check_launch_sizes(&P, 1) == ETEST_EINVAL, "saturated row units accepted");
   }
 }
 

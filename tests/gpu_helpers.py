@@ -10,18 +10,16 @@ against.  Exceedance decisions must agree split by split except for splits
 whose oracle statistic lies within that tolerance of the oracle threshold
 (near-ties); those are returned so a test can report them.
 
-The BF16 form rounds every coordinate to 8 significant bits, which moves a
-distance by about 0.6 * 2^-9 / sqrt(p) of itself on Gaussian data; its 1e-3
-target therefore applies to high-dimensional data (p >= 64 here).  Below that
-the form is checked on data it represents exactly (bf16_exact_pair), where
-only its own arithmetic separates it from the oracle.
+The BF16-refined form's 1e-3 bound holds on Gaussian data at every p: from 64
+coordinates on its Gram reads BF16 operands, below that (where 8-bit coordinates
+alone would move a distance by ~2^-9 / sqrt(p) of itself) the same fp16-pair
+operands as the FP32 form.
 """
 import sys
 
 import numpy as np
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "bf16r": 1e-3}
-BF16_MIN_P = 64
 
 
 def say(*a):
@@ -58,21 +56,3 @@ def compare_run(g, o, prec, label="", tol=None):
     else:
         assert g["count_ge"] == 0 and g["p_value"] == 1.0
     return np.flatnonzero(near)
-
-
-def bf16_exact_pair(X, Y):
-    """Data on which the BF16 form rounds nothing: every coordinate a multiple of 2^-4 in
-    (-16, 16) (at most 8 significant bits), and the pooled sample symmetric about 0 (each
-    drawn row is followed by its negation, plus a zero row for an odd count), so the pooled
-    column mean is exactly 0 and centring changes nothing.  Rows come from the case's
-    Gaussian draws, so shapes and ragged tails are those of the case."""
-    nx, ny = len(X), len(Y)
-    n = nx + ny
-    W = np.concatenate([X, Y]).astype(np.float64)
-    half = np.clip(np.round(W[: n // 2] * 16.0) / 16.0, -15.9375, 15.9375)
-    rows = np.empty((n, W.shape[1]))
-    rows[0:2 * (n // 2):2] = half
-    rows[1:2 * (n // 2):2] = -half
-    if n % 2:
-        rows[-1] = 0.0
-    return rows[:nx].astype(np.float32), rows[nx:].astype(np.float32)

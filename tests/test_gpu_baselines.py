@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2406_06488_amd import _lib, api, inputs
-from tests.gpu_helpers import BF16_MIN_P, bf16_exact_pair, compare_run, say
+from tests.gpu_helpers import compare_run, say
 
 pytestmark = pytest.mark.gpu
 
@@ -29,10 +29,7 @@ def _dev(a, prec):
 
 def _data(nx, ny, p, seed, prec, shift=0.1):
     dt = np.float64 if prec == "f64" else np.float32
-    X, Y = inputs.gaussian_pair(nx, ny, p, seed, mean_shift=shift, dtype=dt)
-    if prec == "bf16r" and p < BF16_MIN_P:
-        X, Y = bf16_exact_pair(X, Y)
-    return X, Y
+    return inputs.gaussian_pair(nx, ny, p, seed, mean_shift=shift, dtype=dt)
 
 
 CASES = [

@@ -6,7 +6,7 @@ import oracle
 from oracle import brute
 from paper_2406_06488_amd import api, inputs
 from paper_2406_06488_amd._lib import EtestError
-from tests.gpu_helpers import BF16_MIN_P, TOL, bf16_exact_pair, compare_run, say
+from tests.gpu_helpers import TOL, compare_run, say
 
 pytestmark = pytest.mark.gpu
 
@@ -99,6 +99,9 @@ CASES = [
     (1, 1, 4, 20, 7, 9, 1.0),
     (40, 33, 1, 300, 8, 10, 0.2),        # p = 1
     (300, 170, 1030, 400, 9, 11, 0.1),   # p above 1024: 33 K slices of 32 in the FP32 Gram
+    (260, 300, 20, 1000, 12, 13, 0.05),  # BF16 form below 64 coordinates: fp16-pair operands
+    (400, 380, 63, 600, 14, 15, 0.05),   # ... the last p before BF16 operands
+    (400, 380, 64, 600, 14, 15, 0.05),   # ... the first p with BF16 operands
 ]
 
 
@@ -109,9 +112,6 @@ def test_full_test_matches_oracle(case, kind, prec):
     nx, ny, p, B, ds, ps_, shift = CASES[case]
     say("full", case, kind, prec, nx, ny, p, B)
     X, Y = _data(nx, ny, p, ds, prec, shift)
-    if prec == "bf16r" and p < BF16_MIN_P:
-        # below its design dimension the BF16 form is pinned on data it represents exactly
-        X, Y = bf16_exact_pair(X, Y)
     gamma = 1.0 / p
     g = api.run(_dev(X, prec), _dev(Y, prec), B, ps_, kind, prec, gamma)
     torch.cuda.synchronize()
@@ -119,6 +119,58 @@ def test_full_test_matches_oracle(case, kind, prec):
     near = compare_run(g, o, prec, "case %d %s %s" % (case, kind, prec))
     if len(near):
         say("near-ties within tolerance:", near.tolist())
+
+
+# --------------------------------------------------------------------------- degenerate data
+
+def _edge_data(name, prec):
+    """Data on which the method's degenerate cases arise (seeded, Gaussian rows)."""
+    g = np.random.Generator(np.random.PCG64(500 + EDGE.index(name)))
+    if name == "same_sample":
+        # X = Y: the observed ED and MMD are exactly 0, every split's statistic is >= 0, so
+        # every split counts (p = 1 in exact arithmetic); splits that pair each row with its
+        # copy tie with the threshold
+        X = g.standard_normal((150, 40))
+        Y = X.copy()
+    elif name == "duplicated_rows":
+        # rows repeated within and across the samples: zero distances off the diagonal
+        base = g.standard_normal((90, 40))
+        X = base[g.integers(0, 90, size=170)]
+        Y = base[g.integers(0, 90, size=130)] + 0.1
+    else:
+        # near-duplicate pairs (y_j = x_j + 1e-4 noise, 80 coordinates, so the BF16 form's
+        # Gram reads BF16 operands) on a common offset of 1000: the Gram-based d^2 of those
+        # pairs cancels to noise, and only the direct difference of the input rows recovers it
+        X = g.standard_normal((160, 80))
+        Y = X[:140] + 1e-4 * g.standard_normal((140, 80))
+        X, Y = X + 1000.0, Y + 1000.0
+    dt = np.float64 if prec == "f64" else np.float32
+    return X.astype(dt), Y.astype(dt)
+
+
+EDGE = ["same_sample", "duplicated_rows", "near_duplicates_offset"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+@pytest.mark.parametrize("name", EDGE)
+def test_degenerate_data_matches_oracle(name, kind, prec):
+    X, Y = _edge_data(name, prec)
+    p = X.shape[1]
+    gamma = 1.0 / p
+    B, seed = 800, 61
+    say("edge", name, kind, prec, X.shape, Y.shape)
+    g = api.run(_dev(X, prec), _dev(Y, prec), B, seed, kind, prec, gamma)
+    torch.cuda.synchronize()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, seed, KIND[kind], gamma)
+    near = compare_run(g, o, prec, "edge %s %s %s" % (name, kind, prec))
+    if prec != "f64":
+        # pairs at (near) zero distance: the form recomputes them as direct FP32 differences
+        assert g["n_refined"] > 0, (name, kind, prec)
+    if name == "same_sample":
+        assert o["statistic"] == 0.0
+        assert np.all(o["perm_stats"] >= o["threshold"])
+    say("  refined %d, near-ties %d: %s" % (g["n_refined"], len(near), near[:20].tolist()))
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
@@ -203,8 +255,6 @@ def test_graph_replay_with_new_inputs(prec):
     for rep, (ds, seed, kind) in enumerate([(31, 5, "ed"), (32, 6, "mmd"), (33, 7, "ed"),
                                             (31, 5, "ed")]):
         X, Y = _data(nx, ny, p, ds, prec, 0.2)
-        if prec == "bf16r":
-            X, Y = bf16_exact_pair(X, Y)  # p < 64: data the form represents exactly
         Xd, Yd = _dev(X, prec), _dev(Y, prec)
         ps = torch.empty(B, dtype=torch.float64, device=DEV)
         req = api.make_request(Xd, Yd, B, seed, kind, prec, 1.0 / p, ps)
@@ -320,3 +370,45 @@ def test_async_call_matches_sync():
     s = api.run(Xd, Yd, 400, 9, "mmd", "f32", 0.05)
     assert a["statistic"] == s["statistic"] and a["count_ge"] == s["count_ge"]
     assert torch.equal(ps, s["perm_stats"])
+
+
+# --------------------------------------------------------------------------- tuned shapes
+
+@pytest.mark.parametrize("prec,kc,cc", [("f32", 1, 1), ("f32", 5, 2), ("f32", 64, 2),
+                                        ("bf16r", 1, 2), ("bf16r", 3, 1), ("bf16r", 64, 2),
+                                        ("f64", 1, 8), ("f64", 7, 3)])
+def test_tuned_work_shapes_match_oracle(prec, kc, cc):
+    """Resampling work shapes installed through the tuning rules (row units of kc column
+    tiles, cc chunks of 256 splits per workgroup) regroup the FP32 partial sums; every
+    shape must still meet the form's tolerance against the oracle."""
+    from paper_2406_06488_amd import autotune
+    nx, ny, p, B = 700, 650, 72, 1500
+    X, Y = _data(nx, ny, p, 71, prec, 0.05)
+    say("tuned shape", prec, kc, cc)
+    autotune.install([{"prec": prec, "n_lo": nx + ny, "n_hi": nx + ny + 1, "kc": kc, "cc": cc}])
+    try:
+        g = api.run(_dev(X, prec), _dev(Y, prec), B, 72, "ed", prec)
+        torch.cuda.synchronize()
+    finally:
+        autotune.clear()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, 72)
+    compare_run(g, o, prec, "tuned %s kc=%d cc=%d" % (prec, kc, cc))
+
+
+def test_autotuner_picks_a_shape_and_results_hold():
+    """The tuner times every candidate shape on one bucket and installs the fastest; a test
+    run under the installed rule matches the oracle."""
+    from paper_2406_06488_amd import autotune
+    nx, ny, p, B = 600, 500, 40, 1024
+    X, Y = _data(nx, ny, p, 81, "f32", 0.05)
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    try:
+        rules = autotune.tune([{"prec": "f32", "n_lo": nx + ny, "n_hi": nx + ny + 1, "X": Xd,
+                                "Y": Yd, "B": B}], reps=1, log=say)
+        assert len(rules) == 1 and (rules[0]["kc"], rules[0]["cc"]) in autotune.MFMA_CANDIDATES
+        g = api.run(Xd, Yd, B, 82, "ed", "f32")
+        torch.cuda.synchronize()
+    finally:
+        autotune.clear()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, 82)
+    compare_run(g, o, "f32", "autotuned")
