@@ -141,6 +141,20 @@ etest_status etest_run(const etest_request* req, void* stream, etest_result* out
 etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* stream);
 etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void* stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving loops,
+   harnesses that forbid allocation): ed_test_async / mmd_test_async (either kind, from
+   req->kind) with the whole workspace in a fixed 128 MiB device array that each GPU the
+   library runs on holds until the process ends.  Allocates nothing (no device, pinned or
+   stream-ordered memory), creates no stream or event, and runs every stage on `stream`;
+   same kernels and results, bit for bit, as the allocating calls.  req, d_out and stream
+   as for ed_test_async; the caller owns X, Y, perm_stats and d_out.  Errors: EINVAL
+   (arguments), ENOMEM when the test's workspace exceeds the array (e.g. 2000 + 2000 rows
+   at p = 1000, B = 10^4 fit; 3000 + 3000 rows at p = 1000 do not) -- checked before any
+   device work, outputs untouched; EDEVICE.  Calls on one GPU share the array: calls that
+   overlap on that GPU (different streams or threads) race; the array keeps the last
+   call's contents, which no call reads before writing. */
+etest_status etest_run_async_noalloc(const etest_request* req, etest_result* d_out, void* stream);
+
 /* ---- Cross tests (permutation-free; the paper's appendix on the cross-ED test) ---- */
 
 typedef struct {

@@ -191,6 +191,21 @@ def run_async(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stats=None):
     return out
 
 
+def run_async_noalloc(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stats=None,
+                      out=None):
+    """run_async() through the entry point that allocates nothing on the library side (its
+    workspace is a fixed device array).  out: a float64 device tensor of 6 for the result
+    (allocated here when None, by torch)."""
+    import torch
+    _check_dev(X, Y, prec)
+    if out is None:
+        out = torch.zeros(6, dtype=torch.float64, device=X.device)
+    req = make_request(X, Y, B, seed, kind, prec, gamma, perm_stats)
+    check(_lib.load().etest_run_async_noalloc(ctypes.byref(req), ctypes.c_void_p(out.data_ptr()),
+                                              _stream()))
+    return out
+
+
 def result_from_device(buf):
     raw = buf.cpu().numpy().tobytes()
     r = Result.from_buffer_copy(raw)

@@ -106,6 +106,10 @@ struct Batch {
 etest_status scratch_region(void** ptr, size_t* bytes);
 void launch_put_desc(const TestDesc& d, const int64_t* offs, TestDesc* dd, int64_t* doffs,
                      hipStream_t st);
+// Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).
+etest_status scratch_region(void** ptr, size_t* bytes);
+void launch_put_desc(const TestDesc& d, const int64_t* offs, TestDesc* dd, int64_t* doffs,
+                     hipStream_t st);
 // Point a plan's descriptor at its buffers inside a device region.
 void assign_pointers(TestPlan& P, char* region, DevResult* result);
 // ED / MMD pairs of a request list that share staging and Gram: partner[s] = t when the
