@@ -95,6 +95,21 @@ def batched_tests(count=256, B=2000):
     return out
 
 
+def device_pair(nx, ny, p, seed, mean_shift=0.0, device="cuda:0"):
+    """X ~ N(0, I_p) (nx rows), Y ~ N(mean_shift * 1, I_p) (ny rows) as float32 device
+    tensors, drawn by torch's device generator seeded with `seed` (X first, then Y).  Used
+    where host generation would not keep up (a request stream); the values are copied back
+    to the host when the oracle checks a result."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    X = torch.randn((nx, p), generator=g, device=device, dtype=torch.float32)
+    Y = torch.randn((ny, p), generator=g, device=device, dtype=torch.float32)
+    if mean_shift:
+        Y += float(mean_shift)
+    return X, Y
+
+
 def serving_stream(rate=200.0, duration=60.0, seed=5):
     """Poisson arrivals; per request nx, ny, p log-uniform, B in {1000, 10000},
     ED or MMD 50/50, Y shifted by delta ~ U[0, 0.1] on every coordinate."""

@@ -1,13 +1,15 @@
-"""Continuous-batching server: results equal the stand-alone calls, admission and errors."""
+"""Continuous-batching server: every served result against the FP64 oracle and equal to the
+stand-alone call, a request mix shaped like the serving stream, admission and errors."""
 import threading
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2406_06488_amd import _lib, api, inputs
 from paper_2406_06488_amd._lib import EtestError
-from tests.gpu_helpers import say
+from tests.gpu_helpers import compare_run, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -38,6 +40,18 @@ def _alone(specs):
     return out
 
 
+_ORACLE = {}
+
+
+def _oracle_of(t, X, Y, B, kind, p):
+    """The oracle's result for spec t (cached: both server configurations serve the same
+    requests)."""
+    if t not in _ORACLE:
+        _ORACLE[t] = oracle.run_test(X.double().cpu().numpy(), Y.double().cpu().numpy(), B,
+                                     400 + t, oracle.ED if kind == "ed" else oracle.MMD, 1.0 / p)
+    return _ORACLE[t]
+
+
 @pytest.mark.parametrize("resident,chunk", [(3, int(2e9)), (16, 0)])
 def test_server_results_equal_standalone(resident, chunk):
     say("server", resident, chunk)
@@ -57,6 +71,10 @@ def test_server_results_equal_standalone(resident, chunk):
             for k in ("statistic", "threshold", "count_ge", "p_value", "n_refined"):
                 assert r[k] == a[k], (t, k, r[k], a[k])
             assert torch.equal(bufs[t], a["perm_stats"]), t
+            nx, ny, p, B, kind, prec = SPECS[t]
+            o = _oracle_of(t, ref[t][0], ref[t][1], B, kind, p)
+            r["perm_stats"] = bufs[t]
+            compare_run(r, o, prec, "served %d" % t)
         st = srv.stats()
         assert st["resident"] == 0 and st["queued"] == 0 and st["bytes_held"] == 0
         assert st["completed"] == len(SPECS)
@@ -138,3 +156,46 @@ def test_server_concurrent_submitters():
         for x in th:
             x.join()
     assert not errors, errors
+
+
+def _serving_mix():
+    """Requests shaped like the serving stream (BF16-refined, ED or Gaussian MMD with
+    sigma^2 = p, mean shift on every coordinate, data seed 100000 + r, split seed
+    200000 + r), at sizes the oracle finishes in seconds: p across the stream's range
+    (10 .. 2000, both sides of the BF16 operand switch at 64), uneven nx, ny up to 3000,
+    B in {1000, 10000}."""
+    g = np.random.Generator(np.random.PCG64(7))
+    shapes = [(2000, 1000, 10, 1000), (300, 250, 10, 10000), (1500, 900, 30, 1000),
+              (400, 520, 30, 10000), (700, 800, 500, 1000), (128, 129, 500, 10000),
+              (600, 300, 2000, 1000), (260, 340, 2000, 10000), (3000, 100, 64, 1000),
+              (100, 2900, 63, 1000), (450, 460, 200, 10000), (1200, 1300, 1000, 1000)]
+    out = []
+    for r, (nx, ny, p, B) in enumerate(shapes):
+        kind = "ed" if r % 2 == 0 else "mmd"
+        delta = float(g.uniform(0.0, 0.1))
+        out.append((r, nx, ny, p, B, kind, delta))
+    return out
+
+
+def test_serving_mix_against_oracle():
+    """Every request of a serving-shaped mix, submitted at once so that their blocks are
+    resident together and their resampling chunks interleave, against the FP64 oracle."""
+    mix = _serving_mix()
+    with api.Server(memory_budget_bytes=8 << 30, max_resident=16,
+                    chunk_updates=int(3e10)) as srv:
+        sub = []
+        for r, nx, ny, p, B, kind, delta in mix:
+            X, Y = _pair(nx, ny, p, 100000 + r, "bf16r", delta)
+            ps = torch.zeros(B, dtype=torch.float64, device=DEV)
+            gamma = 1.0 / p if kind == "mmd" else 0.0
+            sub.append((srv.submit(X, Y, B, 200000 + r, kind, "bf16r", gamma, ps), X, Y, ps))
+        for (rid, X, Y, ps), (r, nx, ny, p, B, kind, delta) in zip(sub, mix):
+            g = srv.wait(rid)
+            g["perm_stats"] = ps
+            say("served", r, nx, ny, p, B, kind, "p =", g["p_value"], "refined", g["n_refined"])
+            o = oracle.run_test(X.double().cpu().numpy(), Y.double().cpu().numpy(), B,
+                                200000 + r, oracle.ED if kind == "ed" else oracle.MMD,
+                                1.0 / p if kind == "mmd" else 1.0)
+            near = compare_run(g, o, "bf16r", "serving mix %d" % r)
+            if len(near):
+                say("  near-ties", near[:20].tolist())
