@@ -343,6 +343,17 @@ etest_status etest_tune_set(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t kc
 /* Remove every tuning rule. */
 etest_status etest_tune_clear(void);
 
+/* Gram workgroup shape for tests of precision prec (ETEST_PREC_F32 or _BF16_REFINED) with
+   pooled size nx + ny in [n_lo, n_hi): 0 = one stored 128 x 128 block tile per workgroup,
+   1 = one 256 x 256 super tile (2 x 2 stored tiles, one wave each) per workgroup, followed
+   by a finishing pass over the stored tiles.  Without a rule: super tiles once there are
+   512 or more of them (pooled size from about 8000 on), block tiles below.  Both shapes add
+   each Gram entry's products in the same order and form every block value, sum and
+   maximum the same way, so results are identical bit for bit; the shape changes speed
+   only.  Process-wide; etest_tune_clear removes these rules too.
+   Errors: EINVAL (prec, range or shape). */
+etest_status etest_tune_set_gram(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t shape);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("etest_profile_read", c_i32, [ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64), c_i32]),
     ("etest_tune_set", c_i32, [c_i32, c_i64, c_i64, c_i32, c_i32]),
     ("etest_tune_clear", c_i32, []),
+    ("etest_tune_set_gram", c_i32, [c_i32, c_i64, c_i64, c_i32]),
 ]
 
 STAGES = ["staging", "blocks", "splits", "sums", "centring", "resampling", "finalize"]

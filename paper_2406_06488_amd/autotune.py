@@ -1,10 +1,12 @@
-"""Autotuner for the resampling stage's work shape.
+"""Autotuner for the work shapes of the Gram and resampling stages.
 
-For each bucket of pooled sample sizes n = nx + ny the tuner times the resampling stage
-(HIP events inside the library) of a representative test under every candidate shape --
-kc column tiles of 128 items and cc chunks of 256 splits per workgroup -- and keeps the
-fastest.  The winning rules are installed with etest_tune_set and can be saved to /
-loaded from a JSON file.
+For each bucket of pooled sample sizes n = nx + ny the tuner times, with HIP events inside
+the library, a representative test under every candidate shape and keeps the fastest:
+  resampling: kc column tiles of 128 items and cc chunks of 256 splits per workgroup
+              (etest_tune_set);
+  Gram:       one 128 x 128 block tile or one 256 x 256 super tile per workgroup
+              (etest_tune_set_gram).
+The winning rules can be saved to / loaded from a JSON file (install() takes both kinds).
 """
 import json
 
@@ -21,11 +23,15 @@ def clear():
 
 
 def install(rules):
-    """rules: list of dicts(prec, n_lo, n_hi, kc, cc)."""
+    """rules: list of dicts(prec, n_lo, n_hi, kc, cc) (resampling) or dicts(prec, n_lo,
+    n_hi, gram_shape) (Gram: 0 = block tiles, 1 = super tiles)."""
     L = _lib.load()
     check(L.etest_tune_clear())
     for r in rules:
-        check(L.etest_tune_set(PRECS[r["prec"]], r["n_lo"], r["n_hi"], r["kc"], r["cc"]))
+        if "gram_shape" in r:
+            check(L.etest_tune_set_gram(PRECS[r["prec"]], r["n_lo"], r["n_hi"], r["gram_shape"]))
+        else:
+            check(L.etest_tune_set(PRECS[r["prec"]], r["n_lo"], r["n_hi"], r["kc"], r["cc"]))
 
 
 def save(rules, path):
@@ -71,4 +77,39 @@ def tune(buckets, reps=3, log=None):
         rules.append({"prec": b["prec"], "n_lo": b["n_lo"], "n_hi": b["n_hi"], "kc": best[1],
                       "cc": best[2], "ms": best[0]})
     install(rules)
+    return rules
+
+
+def _time_blocks(X, Y, kind, prec, gamma, reps):
+    api.run(X, Y, 0, 1, kind, prec, gamma, with_perm_stats=False)  # warm-up
+    api.profile_enable(True, ["blocks"])
+    for _ in range(reps):
+        api.run(X, Y, 0, 1, kind, prec, gamma, with_perm_stats=False)
+    ms, cnt = api.profile_read()["blocks"]
+    api.profile_enable(False)
+    return ms / max(cnt, 1)
+
+
+def tune_gram(buckets, reps=3, log=None, keep=()):
+    """buckets: list of dicts(prec, n_lo, n_hi, X, Y, kind, gamma) of representative tests
+    (FP32 or BF16-refined).  Times the block stage under both Gram workgroup shapes and
+    installs the faster per bucket, together with the rules in `keep`.  Returns the rules."""
+    L = _lib.load()
+    rules = []
+    for b in buckets:
+        best = None
+        for shape in (0, 1):
+            install(list(keep) + [{"prec": b["prec"], "n_lo": b["n_lo"], "n_hi": b["n_hi"],
+                                   "gram_shape": shape}])
+            t = _time_blocks(b["X"], b["Y"], b.get("kind", "ed"), b["prec"], b.get("gamma", 0.0),
+                             reps)
+            if log:
+                log("tune gram %s n[%d,%d) shape=%d: %.4f ms" % (b["prec"], b["n_lo"], b["n_hi"],
+                                                               shape, t))
+            if best is None or t < best[0]:
+                best = (t, shape)
+        rules.append({"prec": b["prec"], "n_lo": b["n_lo"], "n_hi": b["n_hi"],
+                      "gram_shape": best[1], "ms": best[0]})
+    check(L.etest_tune_clear())
+    install(list(keep) + rules)
     return rules

@@ -1,10 +1,10 @@
 // Shared definitions of the gfx950 kernels and the host runtime.
 //
 // Data layout in HBM for one test (n_pad = (tx + ty) * TILE):
-//   W      [n_pad][p_pad]   staged operand rows: X rows, zero rows up to a TILE
-//                           boundary, Y rows, zero rows (column-mean centred for
-//                           the FP32/BF16 forms; FP64 elements, fp16 pairs (hi, lo) of
-//                           the scaled value for the FP32 form, BF16 elements)
+//   W      staged operand rows: X rows, zero rows up to a TILE boundary, Y rows, zero
+//          rows (column-mean centred for the FP32/BF16 forms).  FP64 operands row-major
+//          [n_pad][p_pad]; 16-bit operands (BF16 values, or fp16 pairs hi/lo of the
+//          scaled value) K-blocked [n_pad / T][p_pad / CK][T][32 halves] (blocked_index)
 //   nrm    [n_pad]          squared row norms of the staged rows
 //   D      [ntiles][T][T]   upper tiles (i <= j) of the pooled tile grid: XX upper
 //                           tiles, every XY tile, YY upper tiles -- never a YX tile
@@ -65,9 +65,23 @@ __host__ __device__ inline int gram_operands(int prec, int64_t p) {
   return prec == PREC_F64 ? GOP_F64
          : (prec == PREC_F32 || p < BF16_PAIR_MAX_P) ? GOP_F16PAIR : GOP_BF16;
 }
+// Gram workgroup shapes: one stored 128 x 128 tile per workgroup (four waves of 64 x 64),
+// or one 2 x 2 block of stored tiles (a 256 x 256 super tile: four waves, one tile each).
+enum { GSHAPE_TILE = 0, GSHAPE_SUPER = 1 };
 // K-slice width of each Gram kernel: staged rows are padded to a multiple of it.
 __host__ __device__ inline int gram_k_slice(int gop) {
   return gop == GOP_F64 ? 16 : (gop == GOP_F16PAIR ? 32 : 64);
+}
+// K-blocked layout of the 16-bit operands: every staged row is cut into chunks of 64
+// bytes (BF16: 32 coordinates; fp16 pairs: 16 coordinates, their hi halves then their lo
+// halves), and the chunks of one 128-row tile at one chunk position are contiguous (8 KB),
+// so that a wave loads the chunks of 16 consecutive rows as one contiguous kilobyte.
+constexpr int CHUNK_HALVES = 32;  // 16-bit values per row and chunk
+__host__ __device__ inline int chunk_coords(int gop) { return gop == GOP_BF16 ? 32 : 16; }
+// uint16 index of value c (0..31) of chunk `chunk` of staged row `row`
+__host__ __device__ inline int64_t blocked_index(int64_t row, int64_t chunk, int c,
+                                                 int64_t nchunks) {
+  return (((row / TILE) * nchunks + chunk) * TILE + (row % TILE)) * CHUNK_HALVES + c;
 }
 // Bytes per staged operand element: FP64, one fp16 pair, one BF16 value.
 __host__ __device__ inline int gram_operand_bytes(int gop) {
@@ -94,7 +108,8 @@ __host__ __device__ inline int plane_bytes_per_entry(int pfmt) {
 
 struct TestDesc {
   int32_t kind, prec, pfmt, refine;  // pfmt: plane format of the centred tiles (PLANES_*)
-  int32_t gop, gop_pad;              // gop: operand format of the Gram (GOP_*)
+  int32_t gop, gshape;               // Gram operand format (GOP_*) and workgroup shape
+                                     // (GSHAPE_*)
   int32_t nx, ny, p, p_pad;
   int32_t tx, ty, nt, ntiles;
   int32_t kc, n_rowk, nrowchunks, cc;  // cc: split-column chunks per resampling workgroup

@@ -85,8 +85,8 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// fp16-pair operands: w -> (hi, lo) with hi = fp16(w 2^e), lo = fp16(w 2^e - hi), packed hi in the
-// low half; *r = (hi + lo) 2^-e, the value the Gram's products see (its norm goes to nrm, so
+// fp16-pair operands: w -> (hi, lo) with hi = fp16(w 2^e), lo = fp16(w 2^e - hi), returned
+// packed (hi in the low half; the staging writes them to two planes); *r = (hi + lo) 2^-e, the value the Gram's products see (its norm goes to nrm, so
 // that |a|^2 + |b|^2 - 2 g is formed from one set of operand values).
 __device__ inline uint32_t f16_pair(float w, int e, double* r) {
   const float hs = ldexpf(w, e);
@@ -131,6 +131,10 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
   } else {
     const bool bf = d.gop == GOP_BF16;
     const int e = bf ? 0 : f16_split_exponent(d);
+    // K-blocked 16-bit operands: BF16 value k at (chunk k / 32, slot k % 32); fp16 pair k
+    // hi at (chunk k / 16, slot k % 16), lo at slot 16 + k % 16
+    uint16_t* Wu = (uint16_t*)d.W;
+    const int64_t nch = d.p_pad / chunk_coords(d.gop);
     const float* src = t < 0 ? nullptr : pooled_row<float>(d, t);
     // four columns per lane when every row starts on a 16-byte boundary
     const bool vec = (d.p & 3) == 0 && (((uintptr_t)d.X | (uintptr_t)d.Y) & 15) == 0;
@@ -151,18 +155,22 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
           uint2 o;
           o.x = (uint32_t)h0 | ((uint32_t)h1 << 16);
           o.y = (uint32_t)h2 | ((uint32_t)h3 << 16);
-          *(uint2*)((uint16_t*)d.W + pos * d.p_pad + k) = o;
+          *(uint2*)(Wu + blocked_index(pos, k >> 5, k & 31, nch)) = o;
           const double r0 = bf16_to_f32(h0), r1 = bf16_to_f32(h1);
           const double r2 = bf16_to_f32(h2), r3 = bf16_to_f32(h3);
           nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
         } else {
           double r0, r1, r2, r3;
-          uint4 o;
-          o.x = f16_pair(v.x, e, &r0);
-          o.y = f16_pair(v.y, e, &r1);
-          o.z = f16_pair(v.z, e, &r2);
-          o.w = f16_pair(v.w, e, &r3);
-          *(uint4*)((uint32_t*)d.W + pos * d.p_pad + k) = o;
+          const uint32_t q0 = f16_pair(v.x, e, &r0), q1 = f16_pair(v.y, e, &r1);
+          const uint32_t q2 = f16_pair(v.z, e, &r2), q3 = f16_pair(v.w, e, &r3);
+          uint2 hi, lo;  // the hi plane and the lo plane, four halves each
+          hi.x = (q0 & 0xFFFFu) | (q1 << 16);
+          hi.y = (q2 & 0xFFFFu) | (q3 << 16);
+          lo.x = (q0 >> 16) | (q1 & 0xFFFF0000u);
+          lo.y = (q2 >> 16) | (q3 & 0xFFFF0000u);
+          uint16_t* wp = Wu + blocked_index(pos, k >> 4, k & 15, nch);
+          *(uint2*)wp = hi;
+          *(uint2*)(wp + 16) = lo;
           nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
         }
       }
@@ -176,12 +184,15 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
         }
         if (bf) {
           const uint16_t h = f32_to_bf16_rn(v);
-          ((uint16_t*)d.W)[pos * d.p_pad + k] = h;
+          Wu[blocked_index(pos, k >> 5, k & 31, nch)] = h;
           const float r = bf16_to_f32(h);
           nrm += (double)r * (double)r;
         } else {
           double r;
-          ((uint32_t*)d.W)[pos * d.p_pad + k] = f16_pair(v, e, &r);
+          const uint32_t q = f16_pair(v, e, &r);
+          uint16_t* wp = Wu + blocked_index(pos, k >> 4, k & 15, nch);
+          wp[0] = (uint16_t)(q & 0xFFFFu);
+          wp[16] = (uint16_t)(q >> 16);
           nrm += r * r;
         }
       }

@@ -68,8 +68,14 @@ struct TuneRule {
   int64_t n_lo, n_hi;
   int32_t kc, cc;
 };
+struct GramRule {
+  int32_t prec;
+  int64_t n_lo, n_hi;
+  int32_t shape;
+};
 static std::mutex g_tune_mu;
 static std::vector<TuneRule> g_tune;
+static std::vector<GramRule> g_tune_gram;
 static uint64_t g_tune_gen = 0;  // bumped on every change (guarded by g_tune_mu)
 
 static uint64_t tune_generation() {
@@ -111,6 +117,32 @@ static void tuned_shape(const etest_request& r, int32_t* kc, int32_t* cc) {
     if (nrk * strips * ncr >= 512) break;
     *kc /= 2;
   }
+}
+
+// Workgroups of the super-tile Gram: the upper triangle of the ceil(nt / 2) super grid.
+static int64_t super_tiles(int64_t nt) {
+  const int64_t st = (nt + 1) / 2;
+  return st * (st + 1) / 2;
+}
+
+// Gram workgroup shape of a test: a tuned rule for its precision and pooled size, else
+// super tiles (2 x 2 stored tiles per workgroup) once there are at least
+// GRAM_SUPER_MIN_WG of them -- two rounds of the 256 CUs, as a super-tile workgroup holds
+// a CU alone -- and 128-tile workgroups below.  FP64 blocks have one shape.
+constexpr int64_t GRAM_SUPER_MIN_WG = 512;
+static int gram_shape(const etest_request& r, int64_t nt) {
+  if (r.prec == ETEST_PREC_F64) return GSHAPE_TILE;
+  // the super-tile kernel forms its staged-row offsets within a tile in 32 bits
+  if ((r.p + 64) * 4 * (int64_t)TILE >= (int64_t)1 << 31) return GSHAPE_TILE;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int64_t n = r.nx + r.ny;
+    for (const GramRule& g : g_tune_gram)
+      if (g.prec == r.prec && n >= g.n_lo && n < g.n_hi) return g.shape;
+  }
+  const int env = env_int("ETEST_GRAM_SHAPE", -1, -1, 1);
+  if (env >= 0) return env;
+  return super_tiles(nt) >= GRAM_SUPER_MIN_WG ? GSHAPE_SUPER : GSHAPE_TILE;
 }
 
 TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
@@ -203,9 +235,14 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   P.wg[S_COLPART] = f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0;
   P.wg[S_COLMEAN] = f32like ? (r.p + 63) / 64 : 0;
   P.wg[S_STAGE] = npad / 4;
+  d.gshape = gram_shape(r, d.nt);
+  const bool sup = d.gshape == GSHAPE_SUPER;
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
-  P.wg[S_GRAM_F32] = d.gop == GOP_F16PAIR ? d.ntiles : 0;
-  P.wg[S_GRAM_BF16] = d.gop == GOP_BF16 ? d.ntiles : 0;
+  P.wg[S_GRAM_F32] = d.gop == GOP_F16PAIR && !sup ? d.ntiles : 0;
+  P.wg[S_GRAM_BF16] = d.gop == GOP_BF16 && !sup ? d.ntiles : 0;
+  P.wg[S_GRAM_F32S] = d.gop == GOP_F16PAIR && sup ? super_tiles(d.nt) : 0;
+  P.wg[S_GRAM_BF16S] = d.gop == GOP_BF16 && sup ? super_tiles(d.nt) : 0;
+  P.wg[S_GRAM_FIN] = sup ? d.ntiles : 0;
   P.wg[S_MEMBER] = d.B_pad / MEMBER_SPLITS;
   P.wg[S_ROWSUM] = (2 * npad + 63) / 64;  // two threads per pooled position
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
@@ -321,8 +358,8 @@ etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_per
     b->plans[(size_t)s].partner = u;
     b->plans[(size_t)s].share_z = pairing.share_z[(size_t)s] != 0;
     if (u < 0) continue;
-    for (int k : {S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16})
-      b->plans[(size_t)u].wg[k] = 0;
+    for (int k : {S_COLPART, S_COLMEAN, S_STAGE}) b->plans[(size_t)u].wg[k] = 0;
+    for (int k : GRAM_SLOTS) b->plans[(size_t)u].wg[k] = 0;
     if (pairing.share_z[(size_t)s]) b->plans[(size_t)u].wg[S_MEMBER] = 0;
   }
   return check_launch_sizes(b->plans.data(), b->plans.size());
@@ -439,9 +476,7 @@ void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_o
   end(2, ms);
   if (fork) (void)hipEventRecord(fork->done, ms);
   begin(1, st);
-  launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n, dual);
-  launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n, dual);
-  launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n, dual);
+  launch_gram_slots(offs, total, st, D, n, dual);
   end(1, st);
   begin(3, st);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), n);
@@ -826,6 +861,18 @@ etest_status etest_tune_set(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t kc
 etest_status etest_tune_clear(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune.clear();
+  g_tune_gram.clear();
+  ++g_tune_gen;
+  return ETEST_OK;
+}
+
+etest_status etest_tune_set_gram(int32_t prec, int64_t n_lo, int64_t n_hi, int32_t shape) {
+  if (prec != ETEST_PREC_F32 && prec != ETEST_PREC_BF16_REFINED)
+    return set_error(ETEST_EINVAL, "Gram shape rules apply to the FP32 and BF16-refined forms");
+  if (n_lo < 0 || n_hi <= n_lo || (shape != GSHAPE_TILE && shape != GSHAPE_SUPER))
+    return set_error(ETEST_EINVAL, "bad Gram shape rule");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_gram.push_back(GramRule{prec, n_lo, n_hi, shape});
   ++g_tune_gen;
   return ETEST_OK;
 }
@@ -1027,6 +1074,10 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
   d.ty = (d.ny + TILE - 1) / TILE;
   d.nt = d.tx + d.ty;
   d.ntiles = d.tx * d.ty;
+  // cross tests store no block tile, which the super-tile kernel stages its raw Gram
+  // entries through: they keep one 128-tile workgroup per tile
+  d.gshape = GSHAPE_TILE;
+  const int64_t gram_wg = d.ntiles;
   d.refine = f64 ? 0 : 1;
   d.nrowchunks = (int32_t)((r.nx + r.ny + COLSUM_ROWS - 1) / COLSUM_ROWS);
   d.gamma = r.kind == ETEST_MMD ? r.gamma : 0.0;
@@ -1072,7 +1123,7 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
   // launch tables [0, workgroups] of the stages (a one-test batch)
   const bool f32like = !f64;
   const int64_t wg[5] = {f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0,
-                         f32like ? (r.p + 63) / 64 : 0, npad / 4, d.ntiles, 0};
+                         f32like ? (r.p + 63) / 64 : 0, npad / 4, gram_wg, 0};
   int64_t hoffs[10];
   for (int k = 0; k < 5; ++k) {
     hoffs[2 * k] = 0;
@@ -1095,7 +1146,7 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
     launch_stage(wg[2], st, D, O + 4, 1);
     mark(0, false);
     mark(1, true);
-    launch_gram(d.gop, wg[3], st, D, O + 6, 1, false);
+    launch_gram(d.gop, false, wg[3], st, D, O + 6, 1, false);  // 128-tile shape
     mark(1, false);
     mark(6, true);
     launch_cross_final(st, D);
@@ -1136,9 +1187,7 @@ static void enqueue_blocks(const Batch& b, int m, hipStream_t st) {
   launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), m);
   launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), m);
   launch_stage(total(S_STAGE), st, D, offs(S_STAGE), m);
-  launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), m, false);
-  launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), m, false);
-  launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), m, false);
+  launch_gram_slots(offs, total, st, D, m, false);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), m);
   launch_observed(st, D, nullptr, m);
 }
@@ -1245,9 +1294,7 @@ static etest_status run_precomputed(const etest_request& r, hipStream_t st, etes
   launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), 1);
   mark(2, false);
   mark(1, true);
-  launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), 1, false);
-  launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), 1, false);
-  launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 1, false);
+  launch_gram_slots(offs, total, st, D, 1, false);
   mark(1, false);
   mark(5, true);
   launch_precomp(r.prec == ETEST_PREC_F64, D, d.ntiles, r.B, d.part, st);
@@ -1329,9 +1376,7 @@ static etest_status run_hsic(const etest_hsic_request& h, hipStream_t st, etest_
   launch_stage(tot(S_STAGE), st, D, offs(S_STAGE), 2);
   mark(0, false);
   mark(1, true);
-  launch_gram(GOP_F64, tot(S_GRAM_F64), st, D, offs(S_GRAM_F64), 2, false);
-  launch_gram(GOP_F16PAIR, tot(S_GRAM_F32), st, D, offs(S_GRAM_F32), 2, false);
-  launch_gram(GOP_BF16, tot(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), 2, false);
+  launch_gram_slots(offs, tot, st, D, 2, false);
   mark(1, false);
   mark(2, true);
   launch_permgen(n, h.seed, 0, B, nperm, perms, st);

@@ -16,8 +16,12 @@ void launch_colpart(int64_t blocks, hipStream_t st, const TestDesc* d, const int
 void launch_colmean(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_stage(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_cross_final(hipStream_t st, const TestDesc* d);
-void launch_gram(int gop, int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
-                 int n, bool dual = false);
+// super_tiles: the 256 x 256 kernel, which writes the raw Gram tiles only; the block values
+// then come from launch_gram_finish (one workgroup per stored tile)
+void launch_gram(int gop, bool super_tiles, int64_t blocks, hipStream_t st, const TestDesc* d,
+                 const int64_t* offs, int n, bool dual = false);
+void launch_gram_finish(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs,
+                        int n, bool dual);
 void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
 void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
 void launch_center(bool f64, int64_t blocks, hipStream_t st, const TestDesc* d,
@@ -59,9 +63,26 @@ inline int64_t perm_units(const TestDesc& d, int pcn) {
 
 // Launch slots: one prefix array of workgroup counts per slot.
 enum Slot {
-  S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16, S_MEMBER, S_ROWSUM,
+  S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16, S_GRAM_F32S,
+  S_GRAM_BF16S, S_GRAM_FIN, S_MEMBER, S_ROWSUM,
   S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S2, S_PERM_S3, S_PSTAT, S_COUNT
 };
+
+// Every Gram slot of a launch table: FP64 rows, fp16 pairs and BF16 operands, in 128-tile
+// and super-tile workgroups, then the finish of the super-tile Gram (one workgroup per
+// stored tile).  offs(slot): device launch table; total(slot): its workgroups.
+template <class Offs, class Total>
+inline void launch_gram_slots(Offs offs, Total total, hipStream_t st, const TestDesc* D, int n,
+                              bool dual) {
+  launch_gram(GOP_F64, false, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), n, dual);
+  launch_gram(GOP_F16PAIR, false, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), n, dual);
+  launch_gram(GOP_BF16, false, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), n, dual);
+  launch_gram(GOP_F16PAIR, true, total(S_GRAM_F32S), st, D, offs(S_GRAM_F32S), n, dual);
+  launch_gram(GOP_BF16, true, total(S_GRAM_BF16S), st, D, offs(S_GRAM_BF16S), n, dual);
+  launch_gram_finish(total(S_GRAM_FIN), st, D, offs(S_GRAM_FIN), n, dual);
+}
+constexpr int GRAM_SLOTS[] = {S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16, S_GRAM_F32S, S_GRAM_BF16S,
+                              S_GRAM_FIN};
 
 // Buffer ids inside one test's region.
 enum Buf { B_COLPART, B_COLMEAN, B_W, B_NRM, B_D, B_TSUM, B_TMAX, B_RSUM, B_OBS, B_PLANES, B_Z,
@@ -102,10 +123,6 @@ struct Batch {
   std::vector<size_t> base;      // each test's region offset inside ws
 };
 
-// Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).
-etest_status scratch_region(void** ptr, size_t* bytes);
-void launch_put_desc(const TestDesc& d, const int64_t* offs, TestDesc* dd, int64_t* doffs,
-                     hipStream_t st);
 // Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).
 etest_status scratch_region(void** ptr, size_t* bytes);
 void launch_put_desc(const TestDesc& d, const int64_t* offs, TestDesc* dd, int64_t* doffs,

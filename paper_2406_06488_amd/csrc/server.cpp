@@ -386,9 +386,10 @@ void run_scheduler(etest_server* S) {
       if (q) {
         const TestPlan& P = q->plan;
         if (q->front_pending) {
-          for (int s : {S_COLPART, S_COLMEAN, S_STAGE, S_GRAM_F64, S_GRAM_F32, S_GRAM_BF16,
-                        S_MEMBER, S_ROWSUM, S_CENTER_F64, S_CENTER_SPLIT})
+          for (int s : {S_COLPART, S_COLMEAN, S_STAGE, S_MEMBER, S_ROWSUM, S_CENTER_F64,
+                        S_CENTER_SPLIT})
             w[s] = P.wg[s];
+          for (int s : GRAM_SLOTS) w[s] = P.wg[s];
           w[SEL_FRONT] = 1;
         }
         const int left = q->pc_total - q->pc_done;
@@ -430,9 +431,7 @@ void run_scheduler(etest_server* S) {
         launch_colpart(total(S_COLPART), st, D, offs(S_COLPART), R);
         launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), R);
         launch_stage(total(S_STAGE), st, D, offs(S_STAGE), R);
-        launch_gram(GOP_F64, total(S_GRAM_F64), st, D, offs(S_GRAM_F64), R);
-        launch_gram(GOP_F16PAIR, total(S_GRAM_F32), st, D, offs(S_GRAM_F32), R);
-        launch_gram(GOP_BF16, total(S_GRAM_BF16), st, D, offs(S_GRAM_BF16), R);
+        launch_gram_slots(offs, total, st, D, R, false);
         launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), R);
         launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), R);
         launch_observed(st, D, offs(SEL_FRONT), R);

@@ -13,7 +13,8 @@ void launch_clear_flags(hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_colpart(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_colmean(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_stage(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
-void launch_gram(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int, bool) {}
+void launch_gram(int, bool, int64_t, hipStream_t, const TestDesc*, const int64_t*, int, bool) {}
+void launch_gram_finish(int64_t, hipStream_t, const TestDesc*, const int64_t*, int, bool) {}
 void launch_rowsum(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_observed(hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_center(bool, int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
@@ -82,6 +83,22 @@ static void check_plan(const etest_request& r, bool internal) {
     }
   }
   CHECK(d0.B_pad % NP == 0 && d0.B_pad >= d0.B + 1, "B_pad %lld", (long long)d0.B_pad);
+  {
+    // exactly one Gram slot, matching the test's operand format and workgroup shape (the
+    // super-tile Gram with its finish pass, one workgroup per stored tile)
+    int used = 0;
+    for (int k : GRAM_SLOTS) used += P.wg[k] > 0 ? 1 : 0;
+    CHECK(used == (d0.gshape == GSHAPE_SUPER ? 2 : 1), "%d Gram slots used", used);
+    const int64_t st = (d0.nt + 1) / 2;
+    if (d0.gshape == GSHAPE_SUPER) {
+      CHECK(P.wg[d0.gop == GOP_F16PAIR ? S_GRAM_F32S : S_GRAM_BF16S] == st * (st + 1) / 2,
+            "super-tile Gram grid");
+      CHECK(P.wg[S_GRAM_FIN] == d0.ntiles, "super-tile finish grid");
+    } else
+      CHECK(P.wg[d0.gop == GOP_F64 ? S_GRAM_F64 : d0.gop == GOP_F16PAIR ? S_GRAM_F32 : S_GRAM_BF16]
+                == d0.ntiles, "block-tile Gram grid");
+    CHECK(d0.gshape == GSHAPE_TILE || d0.gop != GOP_F64, "FP64 blocks on super tiles");
+  }
   CHECK(d0.cc >= 1 && d0.cc <= MAX_CC, "cc %d", d0.cc);
   // pointer assignment inside a fake region (pure address arithmetic, never dereferenced)
   char* base = (char*)(uintptr_t)0x10000000000ull;
@@ -206,9 +223,17 @@ static void check_large_grids() {
     Batch b;
     CHECK(build_batch(&r, 1, false, &b) == ETEST_OK, "nt = %lld rejected: %s", (long long)nt,
           etest_last_error());
-    if (!b.plans.empty())
-      CHECK(b.plans[0].wg[S_GRAM_F32] == nt * (nt + 1) / 2, "gram grid of nt = %lld",
+    if (!b.plans.empty()) {
+      // one workgroup per stored tile, or per 2 x 2 super tile of the ceil(nt / 2) grid
+      const int64_t st = (nt + 1) / 2;
+      const TestPlan& P = b.plans[0];
+      const bool tiles = P.wg[S_GRAM_F32] == nt * (nt + 1) / 2 && P.wg[S_GRAM_F32S] == 0;
+      const bool supers = P.wg[S_GRAM_F32S] == st * (st + 1) / 2 && P.wg[S_GRAM_F32] == 0 &&
+                          P.wg[S_GRAM_FIN] == nt * (nt + 1) / 2;
+      CHECK(tiles || supers, "gram grid of nt = %lld", (long long)nt);
+      CHECK(P.wg[S_CENTER_SPLIT] == nt * (nt + 1) / 2, "centring grid of nt = %lld",
             (long long)nt);
+    }
   }
   for (const int64_t n : {(int64_t)46341 * T, (int64_t)65536 * T, (int64_t)2147483647})
     for (int prec : {ETEST_PREC_F64, ETEST_PREC_F32, ETEST_PREC_BF16_REFINED}) {

@@ -412,3 +412,82 @@ def test_autotuner_picks_a_shape_and_results_hold():
         autotune.clear()
     o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, 82)
     compare_run(g, o, "f32", "autotuned")
+
+
+# --------------------------------------------------------------------------- Gram shapes
+
+def _with_gram_shape(shape, prec, n, fn):
+    from paper_2406_06488_amd import autotune
+    autotune.install([{"prec": prec, "n_lo": n, "n_hi": n + 1, "gram_shape": shape}])
+    try:
+        out = fn()
+        torch.cuda.synchronize()
+        return out
+    finally:
+        autotune.clear()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16r"])
+@pytest.mark.parametrize("kind", ["ed", "mmd"])
+@pytest.mark.parametrize("nx,ny,p", [(300, 170, 37), (640, 700, 72), (1000, 900, 130),
+                                     (129, 1, 80), (1, 1, 3), (260, 300, 1030)])
+def test_gram_super_tiles_equal_block_tiles(nx, ny, p, kind, prec):
+    """The 256 x 256 super-tile Gram adds each entry's products in the same order as the
+    128-tile Gram and shares its epilogue: blocks, block sums and every statistic must be
+    identical bit for bit (odd tile grids leave super tiles past the edge; the diagonal
+    super tiles hold a lower tile that is not stored), and both meet the oracle."""
+    X, Y = _data(nx, ny, p, 90 + p, prec, 0.1)
+    Xd, Yd = _dev(X, prec), _dev(Y, prec)
+    gamma = 1.0 / p
+    say("gram shapes", nx, ny, p, kind, prec)
+    blocks = [_with_gram_shape(s_, prec, nx + ny,
+                               lambda: api.blocks(Xd, Yd, kind, prec, gamma)) for s_ in (0, 1)]
+    for a, b in zip(*blocks):
+        assert torch.equal(a, b)
+    runs = [_with_gram_shape(s_, prec, nx + ny,
+                             lambda: api.run(Xd, Yd, 600, 91, kind, prec, gamma)) for s_ in (0, 1)]
+    for k in ("statistic", "threshold", "count_ge", "p_value", "n_refined"):
+        assert runs[0][k] == runs[1][k], k
+    assert torch.equal(runs[0]["perm_stats"], runs[1]["perm_stats"])
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), 600, 91, KIND[kind], gamma)
+    compare_run(runs[1], o, prec, "super tiles %s %s" % (kind, prec))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16r"])
+def test_gram_super_tiles_shared_block_stage(prec):
+    """ED and MMD on the same data in one batch (the ED test's Gram writes both tests'
+    blocks) with super tiles: each result equal to the block-tile run, bit for bit."""
+    nx, ny, p, B = 700, 650, 96, 800
+    X, Y = _data(nx, ny, p, 93, prec, 0.1)
+    Xd, Yd = _dev(X, prec), _dev(Y, prec)
+
+    def pair():
+        outs = [torch.zeros(B, dtype=torch.float64, device=DEV) for _ in range(2)]
+        reqs = [api.make_request(Xd, Yd, B, 94, k, prec, 1.0 / p, o)
+                for k, o in zip(("ed", "mmd"), outs)]
+        res = api.batch(reqs)
+        return res, outs
+    (r0, o0), (r1, o1) = [_with_gram_shape(s_, prec, nx + ny, pair) for s_ in (0, 1)]
+    for t in range(2):
+        for k in ("statistic", "threshold", "count_ge", "p_value", "n_refined"):
+            assert r0[t][k] == r1[t][k], (t, k)
+        assert torch.equal(o0[t], o1[t])
+
+
+def test_gram_shape_autotuner():
+    """The tuner times both Gram shapes on one bucket and installs the faster; a run under
+    the installed rule matches the oracle."""
+    from paper_2406_06488_amd import autotune
+    nx, ny, p = 1500, 1400, 256
+    X, Y = _data(nx, ny, p, 95, "bf16r", 0.05)
+    Xd, Yd = _dev(X, "bf16r"), _dev(Y, "bf16r")
+    try:
+        rules = autotune.tune_gram([{"prec": "bf16r", "n_lo": nx + ny, "n_hi": nx + ny + 1,
+                                     "X": Xd, "Y": Yd}], reps=2, log=say)
+        assert len(rules) == 1 and rules[0]["gram_shape"] in (0, 1)
+        g = api.run(Xd, Yd, 500, 96, "ed", "bf16r")
+        torch.cuda.synchronize()
+    finally:
+        autotune.clear()
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), 500, 96)
+    compare_run(g, o, "bf16r", "gram-shape tuned")
