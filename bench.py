@@ -230,6 +230,52 @@ def cpu_baseline(tests, budget_s, label):
                                                                   "; ".join(detail[:4]))}
 
 
+def golden_parity(wl_name, kind, prec, res, ps):
+    """The served result against the oracle's stored result for the same workload
+    (tests/golden/fullsize_*, written by a script that runs the oracle alone): statistic and
+    threshold error, the largest split error, count and p-value match, near-ties at the
+    form's tolerance and the near-ties whose decision flipped.  None when no stored result
+    exists for this workload."""
+    import numpy as np
+    base = os.path.join(ROOT, "tests", "golden", "fullsize_%s_%s" % (wl_name, kind))
+    try:
+        with open(base + ".json") as f:
+            meta = json.load(f)
+        ops = np.load(base + ".npy", allow_pickle=False)
+    except OSError:
+        return None
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16r": 1e-3}[prec]
+    floor = float(np.mean(np.abs(ops)))
+    err = np.abs(ps - ops) / np.maximum(np.abs(ops), floor)
+    near = np.array(meta["near_ties"]["%g" % tol], dtype=np.int64)
+    flipped = np.flatnonzero((ps >= res["threshold"]) != (ops >= meta["threshold"]))
+    return {"kind": kind, "tolerance": tol,
+            "rel_err_statistic": abs(res["statistic"] - meta["statistic"]) /
+                                 max(abs(meta["statistic"]), floor),
+            "rel_err_threshold": abs(res["threshold"] - meta["threshold"]) /
+                                 max(abs(meta["threshold"]), floor),
+            "max_rel_err_splits": float(err.max()), "count_ge": int(res["count_ge"]),
+            "oracle_count_ge": meta["count_ge"], "p_value": res["p_value"],
+            "oracle_p_value": meta["p_value"], "p_value_match": res["p_value"] == meta["p_value"],
+            "near_ties": int(len(near)), "flipped": flipped.tolist()[:32],
+            "flipped_outside_near_ties": int(np.sum(~np.isin(flipped, near))),
+            "oracle_seconds": meta["oracle_seconds"], "oracle_threads": meta["oracle_threads"]}
+
+
+def cpu_full(X, Y, B, seed, kind, gamma, label):
+    """The oracle's whole test (blocks, observed statistic, all B splits, count, p-value) on
+    the host's cores, timed; returns the baseline record and the oracle's result."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    o = oracle.run_test(X.astype("float64"), Y.astype("float64"), B, seed,
+                        oracle.ED if kind == "ed" else oracle.MMD, gamma, threads)
+    secs = time.perf_counter() - t0
+    return {"value": B / secs, "unit": "permuted statistics/s", "cores": threads,
+            "kind": "oracle", "sample": "%s: the whole test, all %d splits (%.1f s)"
+                                        % (label, B, secs)}, o
+
+
 # ---------------------------------------------------------------------------- workloads
 
 def run_single(args):
@@ -274,10 +320,19 @@ def run_single(args):
     shape = gshape * len(kinds)
     roof, gram_tf, res_tf = roofline(stage, shape, wl.prec, wl.name, gshape)
     value = len(kinds) * wl.B * args.steps / elapsed
-    line = base_line(args, wl.name, value, elapsed, args.steps,
-                     {"f64": "f64", "f32": "f32", "bf16r": "bf16"}[wl.prec],
+    # what the arithmetic is: the FP32 form multiplies fp16 pairs (22 significant bits)
+    # with FP32 accumulation; the BF16-refined form BF16 operands with FP32 accumulation
+    # (fp16 + e4m3 planes in the resampling stage); both reduce in FP64
+    dtype = {"f64": "f64", "f32": "f16x2->f32", "bf16r": "bf16->f32"}[wl.prec]
+    arith = {"f64": "FP64 end to end",
+             "f32": "Gram and resampling on fp16 MFMA from fp16 (hi, lo) pairs of each value "
+                    "(22 significant bits), FP32 accumulation, FP64 reductions",
+             "bf16r": "Gram on BF16 MFMA (fp16 pairs below p = 64) with FP32 accumulation and "
+                      "FP32 recomputation of near pairs; resampling on fp16 + e4m3 planes; "
+                      "FP64 reductions"}[wl.prec]
+    line = base_line(args, wl.name, value, elapsed, args.steps, dtype,
                      {"nx": wl.nx, "ny": wl.ny, "p": wl.p, "B": wl.B, "statistics": kinds,
-                      "precision": wl.prec})
+                      "precision": wl.prec, "arithmetic": arith})
     line.update({"gram_tflops": gram_tf, "resampling_tflops": res_tf,
                  "stage_ms": {k: round(v, 5) for k, v in stage.items()},
                  "stage_ms_live": sorted(live_ms),
@@ -290,6 +345,8 @@ def run_single(args):
             lat.append(time.perf_counter() - t0)
         line["config"]["submission"] = "asynchronous, back to back"
         line["latency_ms_single_test"] = 1e3 * sorted(lat)[len(lat) // 2]
+    # this run's per-split statistics, read before the FP32 form below reuses the outputs
+    host_ps = [ps.cpu().numpy()] if len(kinds) == 1 else [o.cpu().numpy() for o in outs]
     if wl.prec == "bf16r":
         # the plain FP32 form on the same tests
         e32, l32, p32, _ = timed(lambda: step("f32"), max(2, args.steps // 2), 1)
@@ -300,13 +357,25 @@ def run_single(args):
                             "gram_tflops": g32, "resampling_tflops": r32,
                             "stage_ms": {k: round(v, 5) for k, v in s32.items()}}
         line["speedup_vs_f32_form"] = line["f32_form"]["ms_per_step"] / line["ms_per_step"]
-    if not args.no_cpu_baseline:
+    # parity of this run's results with the oracle's stored results for the workload
+    par = [golden_parity(wl.name, k, wl.prec, r, h) for k, r, h in zip(kinds, res, host_ps)]
+    line["oracle_parity"] = par if any(x is not None for x in par) else None
+    if args.no_cpu_baseline:
+        line["cpu_baseline"] = None
+    elif wl.name == "ed_f32_2000x1000_B10000" or wl.prec == "f64":
+        # small enough for the oracle's whole test (about 40 s on 16 host cores)
+        log("cpu baseline (oracle, whole test) ...")
+        line["cpu_baseline"], o = cpu_full(X, Y, wl.B, wl.perm_seed, kinds[0], wl.gamma(),
+                                           wl.name)
+        line["oracle_same_run"] = {"count_ge": o["count_ge"], "p_value": o["p_value"],
+                                   "p_value_match": o["p_value"] == res[0]["p_value"],
+                                   "rel_err_statistic": abs(res[0]["statistic"] - o["statistic"])
+                                   / abs(o["statistic"])}
+    else:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(
             [(X, Y, wl.B, wl.perm_seed, k, wl.gamma()) for k in kinds], args.cpu_seconds,
             wl.name)
-    else:
-        line["cpu_baseline"] = None
     return line
 
 
@@ -620,24 +689,96 @@ def run_hsic(args):
     return line
 
 
+def serving_oracle_check(checked, budget_s, tol=1e-3):
+    """The oracle on the served results kept for checking: per request the blocks, the
+    observed statistic, the threshold and the splits whose served statistic lies within
+    twice the tolerance of the served threshold (the only ones whose decision a result
+    within the tolerance could flip), plus 16 seeded random splits.  The oracle's count is
+    the served count corrected by the oracle's decisions on those splits.  Stops when the
+    time budget is spent; returns the per-request records."""
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = []
+    t_start = time.perf_counter()
+    for rec in checked:
+        if time.perf_counter() - t_start > budget_s:
+            break
+        X, Y, ps, r, w = rec["X"], rec["Y"], rec["ps"], rec["res"], rec["w"]
+        kind = w.kinds[0]
+        k = oracle.ED if kind == "ed" else oracle.MMD
+        gamma = w.gamma() if kind == "mmd" else 1.0
+        XX, YY, XY = oracle.blocks(X, Y, k, gamma, threads)
+        so, _ = oracle.observed(XX, YY, XY, k)
+        to = oracle.threshold(XX, YY, XY, k)
+        g = np.random.Generator(np.random.PCG64(1000 + int(w.name[3:])))
+        rnd = g.integers(0, w.B, size=16)
+        floor_g = float(np.mean(np.abs(ps)))
+        band = np.flatnonzero(np.abs(ps - r["threshold"]) <= 2 * tol * max(abs(r["threshold"]), floor_g))
+        whole_band = len(band) <= 256  # else the p-value is not reconstructed
+        idx = np.unique(np.concatenate([rnd, band if whole_band else band[:0]]))
+        ops = oracle.perm_stats_listed(XX, YY, XY, w.perm_seed, idx, k, threads)
+        floor = float(np.mean(np.abs(ops)))
+        err = np.abs(ps[idx] - ops) / np.maximum(np.abs(ops), floor)
+        o_count, near, flips, flips_out = None, 0, 0, 0
+        if whole_band:
+            ob = ops[np.searchsorted(idx, band)]
+            o_count = int(r["count_ge"] - np.sum(ps[band] >= r["threshold"]) + np.sum(ob >= to))
+            is_near = np.abs(ob - to) <= tol * max(abs(to), floor)
+            near = int(np.sum(is_near))
+            flipped = (ps[band] >= r["threshold"]) != (ob >= to)
+            flips = int(np.sum(flipped))
+            flips_out = int(np.sum(flipped & ~is_near))
+        out.append({"request": w.name, "nx": w.nx, "ny": w.ny, "p": w.p, "B": w.B, "kind": kind,
+                    "rel_err_statistic": abs(r["statistic"] - so) / max(abs(so), floor),
+                    "rel_err_threshold": abs(r["threshold"] - to) / max(abs(to), floor),
+                    "max_rel_err_splits": float(err.max()), "splits_checked": int(len(idx)),
+                    "count_ge": int(r["count_ge"]), "oracle_count_ge": o_count,
+                    "p_value_match": None if o_count is None else o_count == r["count_ge"],
+                    "near_ties": near, "flipped": flips, "flipped_outside_near_ties": flips_out})
+    return out
+
+
 def run_serving(args):
+    """Open-loop Poisson stream through the continuous-batching server (latency, served
+    rate), the oracle on every 50th request with nx, ny <= 5000, then capacity: the first
+    requests submitted all at once, against the same requests run one by one through the
+    synchronous entry point in the plain FP32 form and in the BF16-refined form."""
+    import queue
+
     import numpy as np
     import torch
 
     from paper_2406_06488_amd import api, inputs
     stream = inputs.serving_stream(rate=args.rate, duration=args.duration)
     log("serving: %d requests over %.0f s at %.0f/s" % (len(stream), args.duration, args.rate))
-    g = torch.Generator(device="cuda:0")
-    g.manual_seed(5)
-    half = 1 << 27
-    pool = torch.randn(2 * half, generator=g, device="cuda:0", dtype=torch.float32)
-    torch.cuda.synchronize()
-    rng = np.random.Generator(np.random.PCG64(6))
+    dev = "cuda:0"
+
+    def data_of(w):
+        # per-request data from the request's own seed (data seed 100000 + r)
+        return inputs.device_pair(w.nx, w.ny, w.p, w.data_seed, w.mean_shift, dev)
+
+    def gamma_of(w):
+        return w.gamma() if w.kinds[0] == "mmd" else 0.0
+
+    # producer: each request's data is drawn on a stream of its own before its arrival time
+    # (the data arrive with the request); at most `ahead` requests wait
+    ready = queue.Queue(maxsize=48)
+
+    def producer():
+        gs = torch.cuda.Stream()
+        with torch.cuda.stream(gs):
+            for t_arr, w in stream:
+                X, Y = data_of(w)
+                gs.synchronize()
+                ready.put((X, Y))
+        ready.put(None)
+
+    check_every = 50
     srv = api.Server(memory_budget_bytes=int(args.budget_gb * (1 << 30)), max_resident=64,
                      max_queue=1 << 20)
-    lat = {}
-    submitted = {}
-    done_t = {}
+    lat, submitted, done_t, checked = {}, {}, {}, {}
     lock = threading.Lock()
     stop = threading.Event()
 
@@ -655,21 +796,22 @@ def run_serving(args):
                         done_t[rid] = (now, r)
             time.sleep(0.0005)
 
+    pth = threading.Thread(target=producer, daemon=True)
+    pth.start()
     th = threading.Thread(target=collector, daemon=True)
     th.start()
     t0 = time.perf_counter()
-    for t_arr, w in stream:
-        n_x, n_y = w.nx * w.p, w.ny * w.p
-        ox = int(rng.integers(0, half - n_x))
-        oy = int(rng.integers(0, half - n_y))
-        X = pool[ox:ox + n_x].view(w.nx, w.p)
-        Y = (pool[half + oy:half + oy + n_y] + w.mean_shift).view(w.ny, w.p)
-        torch.cuda.current_stream().synchronize()
+    for idx, (t_arr, w) in enumerate(stream):
+        X, Y = ready.get()
         now = time.perf_counter() - t0
         if now < t_arr:
             time.sleep(t_arr - now)
-        kind = w.kinds[0]
-        rid = srv.submit(X, Y, w.B, w.perm_seed, kind, "bf16r", w.gamma() if kind == "mmd" else 0.0)
+        ps = None
+        if idx % check_every == 0 and w.nx <= 5000 and w.ny <= 5000:
+            ps = torch.empty(w.B, dtype=torch.float64, device=dev)
+        rid = srv.submit(X, Y, w.B, w.perm_seed, w.kinds[0], "bf16r", gamma_of(w), ps)
+        if ps is not None:
+            checked[rid] = {"X": X, "Y": Y, "ps": ps, "w": w}
         with lock:
             submitted[rid] = t0 + t_arr
     t_last = time.perf_counter()
@@ -685,12 +827,70 @@ def run_serving(args):
                      {"rate_per_s": args.rate, "duration_s": args.duration,
                       "requests": len(stream), "nx_ny_range": [100, 20000],
                       "p_range": [10, 2000], "B": [1000, 10000], "statistics": ["ed", "mmd"],
-                      "precision": "bf16r"})
+                      "precision": "bf16r",
+                      "data": "per request N(0, I) / N(delta 1, I) from torch's device "
+                              "generator seeded 100000 + r"})
     line.update({"p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
                  "mean_ms": float(L.mean()), "max_ms": float(L.max()),
                  "tests_per_s": served, "offered_per_s": len(stream) / args.duration,
-                 "submit_lag_s": t_last - t0 - stream[-1][0], "roofline": None,
-                 "cpu_baseline": None})
+                 "submit_lag_s": t_last - t0 - stream[-1][0], "roofline": None})
+
+    # oracle subset
+    recs = []
+    for rid, c in sorted(checked.items(), key=lambda kv: kv[1]["w"].name):
+        recs.append({"X": c["X"].double().cpu().numpy(), "Y": c["Y"].double().cpu().numpy(),
+                     "ps": c["ps"].cpu().numpy(), "res": done_t[rid][1], "w": c["w"]})
+    checked.clear()
+    log("serving: oracle on %d requests (budget %.0f s)" % (len(recs), args.cpu_seconds * 4))
+    par = serving_oracle_check(recs, args.cpu_seconds * 4)
+    line["oracle_parity"] = {
+        "rule": "every %dth request with nx, ny <= 5000; statistic, threshold and the splits "
+                "within twice the 1e-3 tolerance of the threshold plus 16 random splits by the "
+                "FP64 oracle; oracle count = served count corrected by the oracle's decisions "
+                "on those splits" % check_every,
+        "eligible": len(recs), "checked": len(par),
+        "max_rel_err_statistic": max((x["rel_err_statistic"] for x in par), default=None),
+        "max_rel_err_threshold": max((x["rel_err_threshold"] for x in par), default=None),
+        "max_rel_err_splits": max((x["max_rel_err_splits"] for x in par), default=None),
+        "p_value_matches": sum(1 for x in par if x["p_value_match"]),
+        "p_value_unreconstructed": sum(1 for x in par if x["p_value_match"] is None),
+        "near_ties": sum(x["near_ties"] for x in par),
+        "flipped": sum(x["flipped"] for x in par),
+        "flipped_outside_near_ties": sum(x["flipped_outside_near_ties"] for x in par),
+        # every request whose p-value differs, then the first few others
+        "requests": ([x for x in par if x["p_value_match"] is False] +
+                     [x for x in par if x["p_value_match"] is not False])[:12]}
+    recs.clear()
+
+    # capacity: the first requests all at once, and one by one in the FP32 and BF16 forms
+    ncap = min(len(stream), args.capacity_requests)
+    cap = []
+    for _, w in stream[:ncap]:
+        X, Y = data_of(w)
+        cap.append((X, Y, w))
+    torch.cuda.synchronize()
+    with api.Server(memory_budget_bytes=int(args.budget_gb * (1 << 30)), max_resident=64,
+                    max_queue=1 << 20) as srv2:
+        t1 = time.perf_counter()
+        ids = [srv2.submit(X, Y, w.B, w.perm_seed, w.kinds[0], "bf16r", gamma_of(w))
+               for X, Y, w in cap]
+        for rid in ids:
+            srv2.wait(rid)
+        t_srv = time.perf_counter() - t1
+    one = {}
+    for prec in ("f32", "bf16r"):
+        t1 = time.perf_counter()
+        for X, Y, w in cap:
+            api.run(X, Y, w.B, w.perm_seed, w.kinds[0], prec, gamma_of(w), with_perm_stats=False)
+        one[prec] = time.perf_counter() - t1
+    line["capacity"] = {
+        "requests": ncap, "served_all_at_once_tests_per_s": ncap / t_srv,
+        "one_by_one_f32_tests_per_s": ncap / one["f32"],
+        "one_by_one_bf16r_tests_per_s": ncap / one["bf16r"],
+        "served_vs_one_by_one_f32": one["f32"] / t_srv,
+        "served_vs_one_by_one_bf16r": one["bf16r"] / t_srv}
+    log("serving capacity:", json.dumps(line["capacity"]))
+    line["cpu_baseline"] = None
     return line
 
 
@@ -731,6 +931,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--duration", type=float, default=20.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--capacity-requests", type=int, default=600,
+                    help="serving: requests of the capacity comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the plain copy used to scale the HBM byte counters")
     args = ap.parse_args()

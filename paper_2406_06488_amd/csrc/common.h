@@ -33,7 +33,7 @@ constexpr int TMAX_PER_TILE = 2;
 constexpr int NP = 256;              // split columns per resampling chunk
 constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
 constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
-constexpr int MEMBER_SPLITS = 32;    // split columns per split-stream workgroup
+constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
 constexpr int FLAG_COUNT = 4;        // int32 index of the 64-bit (count, finished WGs) word
 constexpr int FLAG_WORDS = 8;
 constexpr int FLAG_XMAX = 6;         // FP32 form: bits of max |input| (a non-negative float)
@@ -43,7 +43,7 @@ constexpr int PC_ROWS = 32;          // pre-computation test: tile rows per stri
 constexpr int PC_STRIPS = TILE / PC_ROWS;
 // Threads per workgroup of the kernels whose launch sizes the host checks.
 constexpr int CM_GROUPS = 16;        // column-mean pass: 64-thread groups per workgroup
-constexpr int MTHREADS = 320;        // split stream: wave 0 scans, waves 1..4 draw
+constexpr int MTHREADS = 256;        // split stream: wave 0 scans, waves 1..3 draw
 constexpr int PERM_THREADS = 512;    // MFMA resampling: 8 waves
 constexpr int PS_GROUPS = 16;        // split statistics: 64-thread groups per workgroup
 // Largest pooled tile grid of one test (tx + ty tiles, nx and ny each padded to whole

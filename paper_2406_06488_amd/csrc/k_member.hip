@@ -57,7 +57,7 @@ struct SplitDraw {
 //
 // One workgroup serves MEMBER_SPLITS consecutive split columns and walks the pooled
 // tiles in order (one tile = 128 padded positions = 4 words).  The scaled draws
-// v_t = floor(u_t (n - t) / 2^64) do not depend on the running count, so waves 1..4
+// v_t = floor(u_t (n - t) / 2^64) do not depend on the running count, so waves 1..3
 // produce the next tile's draws into LDS while wave 0 runs the selection scan (one
 // lane per split) over the current one.  Positions without an item (tile padding)
 // hold v = 0xFFFFFFFF, which is never below need (< 2^31), so the scan is the same
