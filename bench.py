@@ -510,7 +510,47 @@ def run_studies(args):
     line.update({"metric": "tests/s over the Section 5.2 studies (both tests counted)",
                  "unit": "tests/s", "null": null, "power": power, "roofline": None,
                  "cpu_baseline": None})
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], line["oracle_parity"] = studies_oracle_leg()
     return line
+
+
+def studies_oracle_leg(reps=4, B=200):
+    """The CPU leg of the studies: the FP64 oracle's efficient permutation test and cross-ED
+    test on the first replications of the null study (n = 200, p = 100 and 1000; the same
+    data and split seeds as the GPU run), timed; returns the baseline and the comparison."""
+    import numpy as np
+
+    import oracle
+    from paper_2406_06488_amd import studies
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    recs, secs = [], 0.0
+    for p in (100, 1000):
+        res, cross, kept = studies.pvalues(200, 200, p, reps, B=B, seed=1 + p, keep=reps,
+                                           detail=True)
+        for r, c, (X, Y, sd) in zip(res, cross, kept):
+            t0 = time.perf_counter()
+            o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, sd, oracle.ED,
+                                1.0, threads)
+            oc = oracle.cross(X.astype(np.float64), Y.astype(np.float64), oracle.ED, 1.0,
+                              threads)
+            secs += time.perf_counter() - t0
+            floor = float(np.mean(np.abs(o["perm_stats"])))
+            near = int(np.sum(np.abs(o["perm_stats"] - o["threshold"]) <=
+                              1e-5 * max(abs(o["threshold"]), floor)))
+            recs.append({"p": p, "split_seed": sd,
+                         "rel_err_statistic": abs(r["statistic"] - o["statistic"]) /
+                                              max(abs(o["statistic"]), floor),
+                         "count_ge": r["count_ge"], "oracle_count_ge": o["count_ge"],
+                         "p_value_match": r["p_value"] == o["p_value"], "near_ties": near,
+                         "cross_p_value": c, "oracle_cross_p_value": oc["p_value"]})
+    base = {"value": len(recs) / secs, "unit": "tests/s", "cores": threads, "kind": "oracle",
+            "sample": "%d null replications (n = 200, p = 100 and 1000, B = %d): efficient "
+                      "permutation test and cross-ED test, %.1f s" % (len(recs), B, secs)}
+    return base, {"replications": recs,
+                  "p_value_matches": sum(1 for x in recs if x["p_value_match"]),
+                  "max_abs_cross_p_diff": max(abs(x["cross_p_value"] - x["oracle_cross_p_value"])
+                                              for x in recs)}
 
 
 # VALU issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
@@ -842,8 +882,22 @@ def run_serving(args):
                      "ps": c["ps"].cpu().numpy(), "res": done_t[rid][1], "w": c["w"]})
     checked.clear()
     log("serving: oracle on %d requests (budget %.0f s)" % (len(recs), args.cpu_seconds * 4))
-    par = serving_oracle_check(recs, args.cpu_seconds * 4)
-    line["oracle_parity"] = {
+    # the CPU leg: the oracle on the checked requests, timed; its results give the parity
+    if args.no_cpu_baseline:
+        recs.clear()
+        par = None
+    else:
+        t_or = time.perf_counter()
+        par = serving_oracle_check(recs, args.cpu_seconds * 4)
+        t_or = time.perf_counter() - t_or
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        line["cpu_baseline"] = {
+            "value": len(par) / t_or if par else None, "unit": "checked requests/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d requests (every %dth with nx, ny <= 5000): FP64 blocks, observed "
+                      "statistic, threshold and the splits near the threshold, %.1f s"
+                      % (len(par), check_every, t_or)}
+    line["oracle_parity"] = None if par is None else {
         "rule": "every %dth request with nx, ny <= 5000; statistic, threshold and the splits "
                 "within twice the 1e-3 tolerance of the threshold plus 16 random splits by the "
                 "FP64 oracle; oracle count = served count corrected by the oracle's decisions "
@@ -890,7 +944,7 @@ def run_serving(args):
         "served_vs_one_by_one_f32": one["f32"] / t_srv,
         "served_vs_one_by_one_bf16r": one["bf16r"] / t_srv}
     log("serving capacity:", json.dumps(line["capacity"]))
-    line["cpu_baseline"] = None
+    line.setdefault("cpu_baseline", None)
     return line
 
 
