@@ -143,8 +143,10 @@ def roofline(stage_ms, tests, prec, workload=None, gram_tests=None):
 
 
 # a kernel's traffic depends on its source and on the launch shape the runtime picks
-KERNEL_SOURCES = {"k_gram_f16x3": ["k_gram.hip", "common.h", "runtime.cpp"],
-                  "k_gram_bf16": ["k_gram.hip", "common.h", "runtime.cpp"],
+KERNEL_SOURCES = {"k_gram_f16x3": ["k_gram.hip", "k_prep.hip", "common.h", "runtime.cpp"],
+                  "k_gram_bf16": ["k_gram.hip", "k_prep.hip", "common.h", "runtime.cpp"],
+                  "k_gram_super": ["k_gram.hip", "k_prep.hip", "common.h", "runtime.cpp"],
+                  "k_gram_finish": ["k_gram.hip", "common.h", "runtime.cpp"],
                   "k_dist_f64": ["k_gram.hip", "common.h", "runtime.cpp"],
                   "k_perm_mfma": ["k_perm.hip", "common.h", "runtime.cpp"],
                   "k_perm_f64": ["k_perm.hip", "common.h", "runtime.cpp"],
