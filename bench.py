@@ -563,7 +563,8 @@ PRECOMP_OPS_PER_ENTRY = 1   # one FP64 FMA (entry x split bit) per entry and spl
 
 def run_timing(args):
     """Section 5.1 computing-time experiments on one GPU: seconds per test of the standard
-    (Alg. 4), pre-computation (Alg. 5), efficient (Alg. 1) and cross-ED (Alg. 7) energy
+    (Alg. 4), pre-computation (Alg. 5: on symmetric upper tiles, and on the dense pooled
+    matrix as printed), efficient (Alg. 1) and cross-ED (Alg. 7) energy
     distance tests with B = 200, data N_p(0, I); experiment 1: p = 500, nx = ny = 100..1000;
     experiment 2: nx = ny = 200, p = 200..2000.  Wall time of each synchronous call (inputs
     already on the device), averaged over --timing-reps replications (half as many for the
@@ -580,6 +581,9 @@ def run_timing(args):
         "standard": lambda X, Y, q: api.standard(X, Y, B, 1, "ed", q, with_perm_stats=False),
         "precomputed": lambda X, Y, q: api.precomputed(X, Y, B, 1, "ed", q,
                                                        with_perm_stats=False),
+        # Alg. 5 as printed: the dense (nx + ny)^2 pooled matrix, D_YX included
+        "precomputed_dense": lambda X, Y, q: api.precomputed(X, Y, B, 1, "ed", q,
+                                                             with_perm_stats=False, dense=True),
         "efficient": lambda X, Y, q: api.run(X, Y, B, 1, "ed", q, with_perm_stats=False),
         "cross": lambda X, Y, q: api.cross(X, Y, "ed", q),
     }
@@ -612,6 +616,8 @@ def run_timing(args):
                 row["speedup_vs_standard"] = row["standard"]["mean_ms"] / row["efficient"]["mean_ms"]
                 row["speedup_vs_precomputed"] = (row["precomputed"]["mean_ms"] /
                                                  row["efficient"]["mean_ms"])
+                row["speedup_vs_precomputed_dense"] = (row["precomputed_dense"]["mean_ms"] /
+                                                       row["efficient"]["mean_ms"])
                 tab[key] = row
                 log(q, ename, key, {m: round(row[m]["mean_ms"], 3) for m in fns})
             tables["%s_%s" % (q, ename)] = tab

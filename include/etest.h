@@ -196,6 +196,15 @@ etest_status etest_standard(const etest_request* req, void* stream, etest_result
    2 split stream, 5 per-split sums, 6 statistics and p-value. */
 etest_status etest_precomputed(const etest_request* req, void* stream, etest_result* out);
 
+/* Pre-computation permutation test with D_WW as Alg. 5 prints it: the dense (nx + ny)^2
+   pooled matrix, both orders of every pair (D_YX included), computed once by the pooled
+   Gram over every tile of the (tx + ty)^2 tile grid; then for each split the sums over the
+   X*X*, Y*Y* and X*Y* sub-blocks, read entry by entry (the Y*X* entries are skipped), in
+   FP64 and combined into eq. (1) or (2).  Twice the Gram and twice the per-split reads of
+   etest_precomputed; same splits, counting rule, results (up to FP64 summation order),
+   stage timing and errors. */
+etest_status etest_precomputed_dense(const etest_request* req, void* stream, etest_result* out);
+
 /* ---- HSIC independence permutation test (the extension of the paper's discussion) ----
    Paired samples (x_i, y_i), i < n: X is n-by-p and Y n-by-q, row-major, device buffers
    (double for ETEST_PREC_F64, float otherwise).  The Gaussian kernel matrices K of x and

@@ -64,6 +64,7 @@ SIGNATURES = [
     ("etest_hsic", c_i32, [ctypes.POINTER(HsicRequest), c_vp, ctypes.POINTER(Result)]),
     ("etest_permutations", c_i32, [c_i64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     ("etest_precomputed", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
+    ("etest_precomputed_dense", c_i32, [ctypes.POINTER(Request), c_vp, ctypes.POINTER(Result)]),
     ("ed_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("mmd_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("etest_run_async_noalloc", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),

@@ -130,11 +130,15 @@ def standard(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=Tr
     return _baseline("etest_standard", X, Y, B, seed, kind, prec, gamma, with_perm_stats)
 
 
-def precomputed(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True):
+def precomputed(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, with_perm_stats=True,
+                dense=False):
     """Pre-computation permutation test (Alg. 5) on device tensors, synchronous: the pooled
     distance (kernel) matrix once, then per split the sums of the entries its index sets
-    select.  Same splits and result fields as run()."""
-    return _baseline("etest_precomputed", X, Y, B, seed, kind, prec, gamma, with_perm_stats)
+    select.  dense: the pooled matrix as Alg. 5 prints it, (nx + ny)^2 entries with both
+    orders of every pair (otherwise symmetric upper tiles).  Same splits and result fields
+    as run()."""
+    return _baseline("etest_precomputed_dense" if dense else "etest_precomputed", X, Y, B, seed,
+                     kind, prec, gamma, with_perm_stats)
 
 
 def hsic_request(X, Y, B, seed, gamma_x, gamma_y, prec="f32", perm_stats=None):

@@ -149,6 +149,9 @@ struct TestDesc {
   // rectangle of tiles x side by y side is computed, and each tile keeps its row sums over
   // the x2 columns and over the y2 columns apart.
   int32_t cross, cnx1, cny1, cnx2;
+  // Dense pooled matrix (the pre-computation test as the paper prints it): every tile
+  // (i, j) of the nt x nt grid, row-major (tile i * nt + j), both orders of every pair.
+  int32_t dense;
   // Standard permutation test: staging position t reads pooled item rowmap[t] (x* items in
   // increasing order, then y* items), so one split's X* and Y* are staged without copying
   // the data; NULL reads the items in their own order.

@@ -123,6 +123,9 @@ __global__ void __launch_bounds__(1024) k_count(const double* __restrict__ stats
 //                      W_yy += 2 s_y   (each entry stands for (a, b) and (b, a));
 //   diagonal tile:     row in x*: W_xx += s_x, W_xy += s_y;    row in y*: W_yy += s_y
 //                      (the tile holds both orders; x*-y* pairs are taken once).
+// With the dense pooled matrix (Alg. 5 as printed: every tile of the nt x nt grid, D_YX
+// included) every tile holds both orders of its pairs and takes the diagonal-tile rule: the
+// X*X*, Y*Y* and X*Y* sub-blocks are read entry by entry and the Y*X* entries are skipped.
 // Padding entries are 0.  One wave per (tile, 32-row strip, 64 splits): the strip sits in
 // LDS and every lane (one split) reads the same entry, selects it by its own column bit and
 // adds it in FP64.  No matrix product: this is the per-split extraction of Alg. 5.
@@ -140,7 +143,12 @@ __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ des
   const int64_t u = blockIdx.x / sg;  // strip u: tile u / PC_STRIPS, rows 32 (u % PC_STRIPS) ..
   const int t = (int)(u / PC_STRIPS), h = (int)(u % PC_STRIPS);
   int i, j;
-  tile_coords(t, d.nt, &i, &j);
+  if (d.dense) {
+    i = t / d.nt;
+    j = t % d.nt;
+  } else {
+    tile_coords(t, d.nt, &i, &j);
+  }
   const int lane = threadIdx.x;
   {  // the 32 x 128 strip: every 16-byte load of the lane in flight before the LDS stores
     const uint4* src = (const uint4*)((const T*)d.D + (int64_t)t * TILE * TILE +
@@ -170,7 +178,8 @@ __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ des
 #pragma unroll
   for (int q = 0; q < TILE_WORDS; ++q) zc[q] = d.Z[(int64_t)(j * TILE_WORDS + q) * d.B_pad + s];
   const uint32_t zr = d.Z[(int64_t)(i * TILE_WORDS + h) * d.B_pad + s];
-  const bool diag = i == j;
+  // a tile holding both orders of its pairs: a diagonal tile, or any tile of the dense matrix
+  const bool both_orders = d.dense || i == j;
   double wxx = 0.0, wyy = 0.0, wxy = 0.0;
   for (int r = 0; r < PC_ROWS; ++r) {
     const double* row = Ds + r * TILE;
@@ -181,7 +190,7 @@ __global__ void __launch_bounds__(64) k_precomp(const TestDesc* __restrict__ des
     const double sx = (a[0] + a[1]) + (a[2] + a[3]);
     const double sy = (half_tot[r][0] + half_tot[r][1]) - sx;
     const bool member = (zr >> r) & 1u;
-    if (diag) {
+    if (both_orders) {
       if (member) {
         wxx += sx;
         wxy += sy;

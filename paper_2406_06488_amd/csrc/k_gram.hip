@@ -38,6 +38,9 @@ __device__ inline TileCtx tile_ctx(const TestDesc& d, int64_t local) {
   if (d.cross) {  // the rectangle x side by y side, row-major
     c.i = (int)(local / d.ty);
     c.j = d.tx + (int)(local % d.ty);
+  } else if (d.dense) {  // the whole nt x nt grid, row-major
+    c.i = (int)(local / d.nt);
+    c.j = (int)(local % d.nt);
   } else {
     tile_coords(c.t, d.nt, &c.i, &c.j);
   }

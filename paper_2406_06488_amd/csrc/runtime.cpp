@@ -159,8 +159,11 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   d.tx = (int32_t)((r.nx + TILE - 1) / TILE);
   d.ty = (int32_t)((r.ny + TILE - 1) / TILE);
   d.nt = d.tx + d.ty;
-  // below 2^31 for every grid validate_request accepts (nt <= MAX_TILE_GRID)
-  d.ntiles = (int32_t)((int64_t)d.nt * (d.nt + 1) / 2);
+  // below 2^31 for every grid validate_request accepts (nt <= MAX_TILE_GRID), the dense
+  // nt x nt grid included (46340^2 < 2^31)
+  const bool precomp = mode == PLAN_PRECOMP || mode == PLAN_PRECOMP_DENSE;
+  d.dense = mode == PLAN_PRECOMP_DENSE ? 1 : 0;
+  d.ntiles = (int32_t)(d.dense ? (int64_t)d.nt * d.nt : (int64_t)d.nt * (d.nt + 1) / 2);
   // fp16 planes of the centred blocks: hi + lo 2^-11 keeps ~22 significant bits of each
   // centred entry.  One plane (11 bits) is not enough even for the BF16 form: a statistic
   // is a sum with heavy cancellation, and on small tests 11-bit entries move it by ~1e-3.
@@ -217,7 +220,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
     sz[B_PART] = 0;
     sz[B_PSTAT] = 0;
     if (mode == PLAN_BLOCKS) sz[B_Z] = 0;
-    if (mode == PLAN_PRECOMP) {
+    if (precomp) {
       sz[B_PART] = (size_t)d.ntiles * PC_STRIPS * 3 * d.B_pad * 8;
       sz[B_PSTAT] = (size_t)d.B_pad * 8;
     }
@@ -235,7 +238,8 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   P.wg[S_COLPART] = f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0;
   P.wg[S_COLMEAN] = f32like ? (r.p + 63) / 64 : 0;
   P.wg[S_STAGE] = npad / 4;
-  d.gshape = gram_shape(r, d.nt);
+  // the dense grid keeps one 128-tile workgroup per tile
+  d.gshape = d.dense ? GSHAPE_TILE : gram_shape(r, d.nt);
   const bool sup = d.gshape == GSHAPE_SUPER;
   P.wg[S_GRAM_F64] = f64 ? d.ntiles : 0;
   P.wg[S_GRAM_F32] = d.gop == GOP_F16PAIR && !sup ? d.ntiles : 0;
@@ -256,7 +260,7 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
     for (int k : {S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S2, S_PERM_S3, S_PSTAT})
       P.wg[k] = 0;
   if (mode == PLAN_BLOCKS) P.wg[S_MEMBER] = 0;
-  if (mode == PLAN_PRECOMP) P.wg[S_ROWSUM] = 0;
+  if (precomp) P.wg[S_ROWSUM] = 0;
   return P;
 }
 
@@ -1261,14 +1265,16 @@ static etest_status run_standard(const etest_request& r, hipStream_t st, etest_r
   return finish_baseline(d_res, &b, aux, st, e, "standard test", out);
 }
 
-// Pre-computation test: the pooled Gram (D_WW, upper tiles), the split stream, then the
-// per-split class sums of every stored entry and the statistics.
+// Pre-computation test: the pooled Gram (D_WW: upper tiles, or with `dense` the whole
+// nt x nt grid as Alg. 5 prints it), the split stream, then the per-split class sums of
+// every stored entry and the statistics.
 // Stage timing (etest_profile_enable): 0 staging, 1 blocks, 2 split stream, 5 class sums,
 // 6 statistics + p-value.
-static etest_status run_precomputed(const etest_request& r, hipStream_t st, etest_result* out) {
+static etest_status run_precomputed(const etest_request& r, hipStream_t st, etest_result* out,
+                                    bool dense) {
   init_pool_once();
   Batch b;
-  b.plans.push_back(make_plan(r, 0, PLAN_PRECOMP));
+  b.plans.push_back(make_plan(r, 0, dense ? PLAN_PRECOMP_DENSE : PLAN_PRECOMP));
   // one workgroup per (stored tile, 32-row strip, 64 split columns)
   const int64_t groups = (r.B + 1 + 63) / 64;
   if ((int64_t)b.plans[0].d.ntiles * PC_STRIPS > 2147483647LL / groups)
@@ -1453,7 +1459,14 @@ etest_status etest_precomputed(const etest_request* req, void* stream, etest_res
   if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
   etest_status s = validate_request(*req);
   if (s != ETEST_OK) return s;
-  return run_precomputed(*req, (hipStream_t)stream, out);
+  return run_precomputed(*req, (hipStream_t)stream, out, false);
+}
+
+etest_status etest_precomputed_dense(const etest_request* req, void* stream, etest_result* out) {
+  if (!req || !out) return set_error(ETEST_EINVAL, "NULL argument");
+  etest_status s = validate_request(*req);
+  if (s != ETEST_OK) return s;
+  return run_precomputed(*req, (hipStream_t)stream, out, true);
 }
 
 }  // extern "C"

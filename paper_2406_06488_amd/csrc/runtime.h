@@ -106,7 +106,9 @@ etest_status validate_request(const etest_request& r);
 etest_status check_launch_sizes(const TestPlan* plans, size_t n);
 // Plan modes: the efficient test; blocks and observed statistic only (one recomputation of
 // the standard test); pooled blocks, split stream and the pre-computation test's buffers.
-enum PlanMode { PLAN_EFFICIENT = 0, PLAN_BLOCKS = 1, PLAN_PRECOMP = 2 };
+// PLAN_PRECOMP: the pre-computation test on the symmetric upper tiles; PLAN_PRECOMP_DENSE:
+// the same test on the dense pooled matrix (every tile of the nt x nt grid).
+enum PlanMode { PLAN_EFFICIENT = 0, PLAN_BLOCKS = 1, PLAN_PRECOMP = 2, PLAN_PRECOMP_DENSE = 3 };
 TestPlan make_plan(const etest_request& r, int64_t kc_override = 0, int mode = PLAN_EFFICIENT);
 
 // A set of tests laid out in one device workspace, ready to launch.

@@ -127,7 +127,18 @@ static void check_mode_plan(const etest_request& r, int mode) {
   need[B_D] = (size_t)d0.ntiles * TILE * TILE * (f64 ? 8 : 4);
   need[B_RSUM] = (size_t)npad * 16;
   need[B_TSUM] = (size_t)d0.ntiles * 2 * TILE * 8;
-  if (mode == PLAN_PRECOMP) {
+  const bool precomp = mode == PLAN_PRECOMP || mode == PLAN_PRECOMP_DENSE;
+  // the dense pooled matrix: every tile of the nt x nt grid, one 128-tile Gram workgroup each
+  const int64_t tiles = mode == PLAN_PRECOMP_DENSE ? (int64_t)d0.nt * d0.nt
+                                                   : (int64_t)d0.nt * (d0.nt + 1) / 2;
+  CHECK(d0.ntiles == tiles && d0.dense == (mode == PLAN_PRECOMP_DENSE ? 1 : 0),
+        "mode %d tile count %d", mode, d0.ntiles);
+  if (mode == PLAN_PRECOMP_DENSE) {
+    CHECK(d0.gshape == GSHAPE_TILE, "dense grid on super tiles");
+    CHECK(P.wg[f64 ? S_GRAM_F64 : d0.gop == GOP_F16PAIR ? S_GRAM_F32 : S_GRAM_BF16] == tiles,
+          "dense Gram grid");
+  }
+  if (precomp) {
     // k_precomp reads Z columns below ceil((B + 1) / 64) * 64 and writes strip sums of the
     // columns up to B; k_precomp_stat writes B + 1 statistics
     const int64_t cols = (r.B + 1 + 63) / 64 * 64;
@@ -149,8 +160,8 @@ static void check_mode_plan(const etest_request& r, int mode) {
   CHECK(P.size[B_PLANES] == 0, "mode %d keeps centred planes", mode);
   for (int k : {S_CENTER_F64, S_CENTER_SPLIT, S_PERM_F64, S_PERM_S2, S_PERM_S3, S_PSTAT})
     CHECK(P.wg[k] == 0, "mode %d launches slot %d", mode, k);
-  CHECK((P.wg[S_MEMBER] > 0) == (mode == PLAN_PRECOMP), "mode %d split stream", mode);
-  CHECK(P.bytes < make_plan(r).bytes || r.B == 0 || mode == PLAN_PRECOMP,
+  CHECK((P.wg[S_MEMBER] > 0) == precomp, "mode %d split stream", mode);
+  CHECK(P.bytes < make_plan(r).bytes || r.B == 0 || precomp,
         "blocks-only plan not smaller than the full plan");
 }
 
@@ -290,6 +301,7 @@ int main() {
             if (!internal && !with_out) {
               check_mode_plan(r, PLAN_BLOCKS);
               check_mode_plan(r, PLAN_PRECOMP);
+              check_mode_plan(r, PLAN_PRECOMP_DENSE);
             }
           }
   // one-sample plans of the HSIC test (ny = 0: the Gram covers the rows of one sample)

@@ -45,7 +45,7 @@ def test_next_row_calls_reject_before_device():
     L = _lib.load()
     r = _lib.Result()
     bad = _lib.Request(0, _lib.PREC_F32, 0, 5, 3, 10, 1, 0.0, 8, 8, None)  # nx = 0
-    for fn in (L.etest_standard, L.etest_precomputed):
+    for fn in (L.etest_standard, L.etest_precomputed, L.etest_precomputed_dense):
         assert fn(ctypes.byref(bad), None, ctypes.byref(r)) == _lib.EINVAL
         assert fn(None, None, ctypes.byref(r)) == _lib.EINVAL
     cr = _lib.CrossResult()

@@ -19,7 +19,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 DEV = "cuda:0"
 KIND = {"ed": oracle.ED, "mmd": oracle.MMD}
-METHODS = {"standard": api.standard, "precomputed": api.precomputed}
+METHODS = {"standard": api.standard, "precomputed": api.precomputed,
+           "precomputed_dense": lambda *a, **k: api.precomputed(*a, dense=True, **k)}
 
 
 def _dev(a, prec):
@@ -45,7 +46,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("method", ["standard", "precomputed"])
+@pytest.mark.parametrize("method", ["standard", "precomputed", "precomputed_dense"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16r"])
 @pytest.mark.parametrize("kind", ["ed", "mmd"])
 @pytest.mark.parametrize("case", range(len(CASES)))
@@ -73,18 +74,19 @@ def test_three_tests_agree_split_by_split(kind):
     gamma = 1.0 / p
     e = api.run(Xd, Yd, B, 77, kind, "f64", gamma)
     pc = api.precomputed(Xd, Yd, B, 77, kind, "f64", gamma)
+    pd = api.precomputed(Xd, Yd, B, 77, kind, "f64", gamma, dense=True)
     st = api.standard(Xd, Yd, B, 77, kind, "f64", gamma)
     torch.cuda.synchronize()
     ref = e["perm_stats"].cpu().numpy()
     scale = max(float(np.mean(np.abs(ref))), abs(e["statistic"]))
-    for name, r in (("precomputed", pc), ("standard", st)):
+    for name, r in (("precomputed", pc), ("precomputed_dense", pd), ("standard", st)):
         v = r["perm_stats"].cpu().numpy()
         assert np.abs(v - ref).max() <= 1e-12 * scale, (name, np.abs(v - ref).max(), scale)
         assert abs(r["statistic"] - e["statistic"]) <= 1e-12 * scale, name
         assert r["count_ge"] == e["count_ge"] and r["p_value"] == e["p_value"], name
 
 
-@pytest.mark.parametrize("method", ["standard", "precomputed"])
+@pytest.mark.parametrize("method", ["standard", "precomputed", "precomputed_dense"])
 def test_zero_and_one_permutations(method):
     X, Y = _data(20, 30, 5, 1, "f32")
     g = METHODS[method](_dev(X, "f32"), _dev(Y, "f32"), 0, 1, "ed", "f32")
@@ -94,7 +96,8 @@ def test_zero_and_one_permutations(method):
     compare_run(g, o, "f32")
 
 
-@pytest.mark.parametrize("method", ["etest_standard", "etest_precomputed"])
+@pytest.mark.parametrize("method", ["etest_standard", "etest_precomputed",
+                                    "etest_precomputed_dense"])
 def test_nonfinite_input_rejected_and_outputs_untouched(method):
     X, Y = _data(50, 40, 6, 2, "f32")
     Y[7, 1] = np.inf
@@ -107,7 +110,8 @@ def test_nonfinite_input_rejected_and_outputs_untouched(method):
     assert torch.all(ps == 7.0)
 
 
-@pytest.mark.parametrize("method", ["etest_standard", "etest_precomputed"])
+@pytest.mark.parametrize("method", ["etest_standard", "etest_precomputed",
+                                    "etest_precomputed_dense"])
 def test_bad_arguments_rejected(method):
     fn = getattr(_lib.load(), method)
     X, Y = _data(10, 10, 3, 2, "f32")
