@@ -31,17 +31,24 @@ __global__ void __launch_bounds__(64) k_rowsum(const TestDesc* __restrict__ desc
     const double* t = ts + (int64_t)tile_index(j, i, d.nt) * TSUM_STRIDE;
     return t[TILE + r] + t[2 * TILE + r];
   };
+  // unrolled so that several tile sums are in flight; the additions stay in order of j
   if (!cross) {
     const int b0 = isx ? 0 : d.tx, b1 = isx ? d.tx : d.nt;  // own block's tile range
+#pragma unroll 8
     for (int j = b0; j < i; ++j) s += colsum(j);
+#pragma unroll 8
     for (int j = i; j < b1; ++j) s += rowsum(j);
   } else if (isx) {
+#pragma unroll 8
     for (int j = d.tx; j < d.nt; ++j) s += rowsum(j);
   } else {
+#pragma unroll 8
     for (int j = 0; j < d.tx; ++j) s += colsum(j);
   }
   d.rsum[pos * 2 + (cross ? 1 : 0)] = s;
 }
+
+constexpr int OBS_BATCH = 8;
 
 struct Neu {
   double s, c;
@@ -63,12 +70,26 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
   const int tid = threadIdx.x;
   Neu sxx{0, 0}, syy{0, 0}, sxy{0, 0};
   const int64_t xend = (int64_t)d.tx * TILE, npad = (int64_t)d.nt * TILE;
-  for (int64_t pos = tid; pos < npad; pos += 256) {
-    if (pos < xend) {
-      sxx.add(d.rsum[pos * 2]);
-      sxy.add(d.rsum[pos * 2 + 1]);
-    } else {
-      syy.add(d.rsum[pos * 2]);
+  // The loads of OBS_BATCH positions are issued together before any of them is added (the
+  // row sums were just written by other XCDs, so each load waits on a far cache); the
+  // additions keep the order pos = tid, tid + 256, ... .
+  for (int64_t base = tid; base < npad; base += 256 * OBS_BATCH) {
+    double a[OBS_BATCH], b[OBS_BATCH];
+#pragma unroll
+    for (int u = 0; u < OBS_BATCH; ++u) {
+      const int64_t pos = base + 256 * u;
+      a[u] = pos < npad ? d.rsum[pos * 2] : 0.0;
+      b[u] = pos < xend ? d.rsum[pos * 2 + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < OBS_BATCH; ++u) {
+      const int64_t pos = base + 256 * u;
+      if (pos < xend) {
+        sxx.add(a[u]);
+        sxy.add(b[u]);
+      } else if (pos < npad) {
+        syy.add(a[u]);
+      }
     }
   }
   red[0][tid][0] = sxx.s; red[0][tid][1] = sxx.c;
@@ -101,8 +122,16 @@ __global__ void __launch_bounds__(256) k_observed(const TestDesc* __restrict__ d
   // plane value inside the fp16 range.
   __shared__ float mx[256];
   float m = 0.0f;
-  if (d.prec != PREC_F64)
-    for (int t = tid; t < d.ntiles * TMAX_PER_TILE; t += 256) m = fmaxf(m, d.tmax[t]);
+  if (d.prec != PREC_F64) {
+    const int nmax = d.ntiles * TMAX_PER_TILE;
+    for (int base = tid; base < nmax; base += 256 * OBS_BATCH) {
+      float v[OBS_BATCH];
+#pragma unroll
+      for (int u = 0; u < OBS_BATCH; ++u) v[u] = base + 256 * u < nmax ? d.tmax[base + 256 * u] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < OBS_BATCH; ++u) m = fmaxf(m, v[u]);
+    }
+  }
   mx[tid] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
