@@ -238,12 +238,15 @@ __global__ void __launch_bounds__(PERM_THREADS) k_perm_mfma(const TestDesc* __re
     double q = 0.0;
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-      const uint32_t wz = wzf[nb][mb];
+      // bit (8 (e / 4) + 4 h + e % 4) of the word weights element e; a sign-extended one-bit
+      // field is an all-ones or all-zero mask, so a cleared bit adds +0.0 as before
+      const uint32_t wz = wzf[nb][mb] >> (4 * h);
       float f = 0.0f;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int bit = 8 * (e >> 2) + 4 * h + (e & 3);
-        f += ((wz >> bit) & 1u) ? acc[mb][nb][e] : 0.0f;
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)wz, 8 * (e >> 2) + (e & 3), 1);
+        const float x = acc[mb][nb][e];  // a copy: a vector element has no address of its own
+        f += __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) & m);
       }
       q += (double)f;
     }
