@@ -449,6 +449,15 @@ void free_batch(Batch* b, hipStream_t st, bool stream_ordered) {
   b->ws = nullptr;
 }
 
+// Split stream after the block stage once it has more workgroups than the chip holds at
+// once (8 per CU of MI355X's 256).  ETEST_SPLIT_LATE = 0 / 1 forces either order.
+constexpr int64_t SPLIT_EARLY_MAX_WG = 8 * 256;
+static bool split_late(int64_t member_wg) {
+  static const int env = env_int("ETEST_SPLIT_LATE", -1, -1, 1);
+  if (env >= 0) return env == 1;
+  return member_wg > SPLIT_EARLY_MAX_WG;
+}
+
 void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_offs, int n,
                     bool dual, hipStream_t st, const uint32_t* import_words, int64_t import_bpad,
                     const StageEvents* ev, const Fork* fork) {
@@ -466,22 +475,32 @@ void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_o
   launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), n);
   launch_stage(total(S_STAGE), st, D, offs(S_STAGE), n);
   end(0, st);
-  // split stream: independent of the data, so it runs beside the block stage, whose grid
-  // leaves room on the CUs (it is forked after staging, a short memory-bound stage)
+  // Split stream: independent of the data, so it runs beside other stages.  A stream that
+  // fits on the chip at once (up to SPLIT_EARLY_MAX_WG workgroups: each one's walk over the
+  // pooled items is latency-bound) is forked after staging, a short memory-bound stage, and
+  // runs beside the block stage, whose grid leaves room on the CUs.  A larger one (many
+  // tests in one launch) keeps every CU's vector ALU busy for its whole duration and would
+  // slow the block stage by about as much as it overlaps; it is forked after the block stage
+  // and runs beside the sums and the centring, which are bound by memory.
   hipStream_t ms = st;
-  if (fork) {
-    (void)hipEventRecord(fork->start, st);
-    (void)hipStreamWaitEvent(fork->aux, fork->start, 0);
-    ms = fork->aux;
-  }
-  begin(2, ms);
-  if (import_words) launch_member_import(import_bpad, ms, D, import_words);
-  else launch_member(total(S_MEMBER), ms, D, offs(S_MEMBER), n);
-  end(2, ms);
-  if (fork) (void)hipEventRecord(fork->done, ms);
+  const bool late = fork && split_late(total(S_MEMBER));
+  auto split = [&]() {
+    if (fork) {
+      (void)hipEventRecord(fork->start, st);
+      (void)hipStreamWaitEvent(fork->aux, fork->start, 0);
+      ms = fork->aux;
+    }
+    begin(2, ms);
+    if (import_words) launch_member_import(import_bpad, ms, D, import_words);
+    else launch_member(total(S_MEMBER), ms, D, offs(S_MEMBER), n);
+    end(2, ms);
+    if (fork) (void)hipEventRecord(fork->done, ms);
+  };
+  if (!late) split();
   begin(1, st);
   launch_gram_slots(offs, total, st, D, n, dual);
   end(1, st);
+  if (late) split();
   begin(3, st);
   launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), n);
   launch_observed(st, D, nullptr, n);
