@@ -136,8 +136,13 @@ etest_status mmd_test_f64(const double* X, int64_t nx, const double* Y, int64_t 
 etest_status etest_run(const etest_request* req, void* stream, etest_result* out);
 
 /* Enqueue one test on `stream` and return without waiting.  d_out is a device pointer to
-   one etest_result, written when the stream reaches the end of the work.  Scratch memory
-   is taken from and returned to the stream-ordered allocator. */
+   one etest_result, written by the pass's last kernel; it must stay valid until the stream
+   has reached the end of the work.  Scratch memory: one workspace per (device, stream),
+   taken from the stream-ordered allocator on the first call and kept for the calls that
+   follow on that stream (they run in stream order, so each reuses it without waiting for
+   the previous one); a call that needs more replaces it, the old one being freed in
+   stream order.  The workspace is held until the process ends.  Under stream capture the
+   call allocates and frees its own workspace instead. */
 etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* stream);
 etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void* stream);
 

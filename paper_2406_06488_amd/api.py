@@ -188,7 +188,7 @@ def run_async(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stats=None):
     etest_result (6 x 8 bytes).  Use result_from_device() after synchronising."""
     import torch
     _check_dev(X, Y, prec)
-    out = torch.zeros(6, dtype=torch.float64, device=X.device)
+    out = torch.empty(6, dtype=torch.float64, device=X.device)  # written by the library
     req = make_request(X, Y, B, seed, kind, prec, gamma, perm_stats)
     fn = _lib.load().ed_test_async if _kind(kind) == ED else _lib.load().mmd_test_async
     check(fn(ctypes.byref(req), ctypes.c_void_p(out.data_ptr()), _stream()))
@@ -203,7 +203,7 @@ def run_async_noalloc(X, Y, B, seed, kind="ed", prec="f32", gamma=0.0, perm_stat
     import torch
     _check_dev(X, Y, prec)
     if out is None:
-        out = torch.zeros(6, dtype=torch.float64, device=X.device)
+        out = torch.empty(6, dtype=torch.float64, device=X.device)  # written by the library
     req = make_request(X, Y, B, seed, kind, prec, gamma, perm_stats)
     check(_lib.load().etest_run_async_noalloc(ctypes.byref(req), ctypes.c_void_p(out.data_ptr()),
                                               _stream()))

@@ -136,6 +136,10 @@ struct TestDesc {
   // flags[FLAG_COUNT..+1]: exceedance count (low half) and finished workgroups (high half)
   double* perm_out;
   DevResult* result;
+  // Asynchronous single-test calls: the caller's result buffer, which the final kernel
+  // fills with the result's leading six words (the etest_result fields) beside *result
+  // (NULL: none).
+  double* out6;
   // Shared block stage: an energy-distance test whose Gram also yields the Gaussian-kernel
   // blocks of an MMD test on the same data (pD != nullptr) writes that test's D, tile sums,
   // tile max and flags too.

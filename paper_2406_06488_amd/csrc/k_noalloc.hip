@@ -27,10 +27,12 @@ struct DescArgs {
   int64_t offs[S_COUNT * 2];
 };
 
+// It also clears the test's flag words, which every later kernel of the pass may update.
 __global__ void k_put_desc(DescArgs a, TestDesc* __restrict__ dd, int64_t* __restrict__ doffs) {
   const int t = threadIdx.x;
   if (t == 0) *dd = a.d;
   if (t < S_COUNT * 2) doffs[t] = a.offs[t];
+  if (t < FLAG_WORDS) a.d.flags[t] = 0;
 }
 
 etest_status scratch_region(void** ptr, size_t* bytes) {
@@ -103,11 +105,10 @@ extern "C" etest_status etest_run_async_noalloc(const etest_request* req, etest_
     ho[2 * k + 1] = P.wg[k];
   }
   hipStream_t st = (hipStream_t)stream;
+  P.d.out6 = (double*)d_out;  // the final kernel writes the result there too
   launch_put_desc(P.d, ho, dd, doffs, st);
-  enqueue_stages(dd, doffs, ho, 1, false, st, nullptr, 0, nullptr, nullptr);
-  // etest_result is the leading part of DevResult
-  hipError_t e = hipMemcpyAsync(d_out, dres, sizeof(etest_result), hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipGetLastError();
+  enqueue_stages(dd, doffs, ho, 1, false, st, nullptr, 0, nullptr, nullptr, false);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(ETEST_EDEVICE, std::string("enqueue: ") + hipGetErrorString(e));
   return ETEST_OK;
 }

@@ -123,6 +123,12 @@ struct Batch {
   DevResult* d_results = nullptr;
   double* d_perm = nullptr;      // internal perm-stat buffers (host-output calls)
   std::vector<size_t> base;      // each test's region offset inside ws
+  // ws comes from the stream's cached workspace (stream_workspace) and is not freed with
+  // the batch
+  bool cached = false;
+  // single test: the descriptor and launch table go to the device as kernel arguments
+  // (launch_put_desc, which also clears the flag words) instead of two host copies
+  bool desc_by_kernel = false;
 };
 
 // Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).
@@ -166,9 +172,10 @@ struct Fork {
 // same tables on the host in h_offs: [S_COUNT][n + 1] prefix sums of workgroups) are in
 // device memory.  dual: some ED test also writes its MMD partner's blocks.  import_words:
 // caller splits for a single test of B_pad import_bpad (or null).
+// clear_flags false: the flag words were cleared already (launch_put_desc).
 void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_offs, int n,
                     bool dual, hipStream_t st, const uint32_t* import_words, int64_t import_bpad,
-                    const StageEvents* ev, const Fork* fork);
+                    const StageEvents* ev, const Fork* fork, bool clear_flags = true);
 // Enqueue every stage.  import_words: caller splits for a single test (or null).
 void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words = nullptr,
                    const StageEvents* events = nullptr, const Fork* fork = nullptr);

@@ -36,6 +36,7 @@ void launch_hsic_prep(bool, const TestDesc*, int64_t, void*, void*, double*, dou
 void launch_hsic_terms(bool, const void*, const void*, int64_t, const int32_t*, int64_t,
                        const double*, const double*, double*, hipStream_t) {}
 void launch_hsic_stat(const double*, int64_t, int64_t, const double*, double*, hipStream_t) {}
+void launch_put_desc(const TestDesc&, const int64_t*, TestDesc*, int64_t*, hipStream_t) {}
 }  // namespace et
 
 using namespace et;
