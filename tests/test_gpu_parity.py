@@ -372,6 +372,41 @@ def test_async_call_matches_sync():
     assert torch.equal(ps, s["perm_stats"])
 
 
+def test_async_calls_back_to_back_reuse_the_stream_workspace():
+    """Asynchronous calls keep one workspace per (device, stream) and reuse it in stream
+    order.  Back-to-back calls with no synchronisation between them -- growing (the
+    workspace is replaced while earlier work is still queued), shrinking, on a second
+    stream, both statistics and all three forms -- must each equal the synchronous call
+    bit for bit."""
+    cases = [(150, 140, 20, "f32", "ed"), (700, 650, 90, "f32", "ed"),
+             (130, 170, 37, "bf16r", "mmd"), (900, 820, 64, "bf16r", "ed"),
+             (60, 75, 12, "f64", "ed"), (150, 140, 20, "f32", "ed")]
+    B = 600
+    data, outs = [], []
+    side = torch.cuda.Stream()
+    for k, (nx, ny, p, prec, kind) in enumerate(cases):
+        X, Y = _data(nx, ny, p, 80 + k, prec)
+        Xd, Yd = _dev(X, prec), _dev(Y, prec)
+        ps = torch.zeros(B, dtype=torch.float64, device=DEV)
+        gamma = 1.0 / p if kind == "mmd" else 0.0
+        data.append((Xd, Yd, prec, kind, gamma, ps))
+    say("async back to back", len(cases), "tests")
+    torch.cuda.synchronize()
+    for k, (Xd, Yd, prec, kind, gamma, ps) in enumerate(data):
+        if k == 3:  # one on a second stream, between the others
+            with torch.cuda.stream(side):
+                outs.append(api.run_async(Xd, Yd, B, 30 + k, kind, prec, gamma, ps))
+        else:
+            outs.append(api.run_async(Xd, Yd, B, 30 + k, kind, prec, gamma, ps))
+    torch.cuda.synchronize()
+    for k, (Xd, Yd, prec, kind, gamma, ps) in enumerate(data):
+        a = api.result_from_device(outs[k])
+        s = api.run(Xd, Yd, B, 30 + k, kind, prec, gamma)
+        assert a["statistic"] == s["statistic"] and a["count_ge"] == s["count_ge"], k
+        assert a["p_value"] == s["p_value"] and a["threshold"] == s["threshold"], k
+        assert torch.equal(ps, s["perm_stats"]), k
+
+
 # --------------------------------------------------------------------------- tuned shapes
 
 @pytest.mark.parametrize("prec,kc,cc", [("f32", 1, 1), ("f32", 5, 2), ("f32", 64, 2),
