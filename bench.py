@@ -314,6 +314,7 @@ def run_single(args):
     elapsed, live, prof, res = timed(step, args.steps, args.warmup)
     if len(kinds) == 1:
         res = [api.result_from_device(r) for r in res]
+
     stage = per_launch(prof)
     live_ms = {k: v for k, v in per_launch(live).items() if k in LIVE_STAGES}
     stage.update(live_ms)
@@ -347,6 +348,8 @@ def run_single(args):
             lat.append(time.perf_counter() - t0)
         line["config"]["submission"] = "asynchronous, back to back"
         line["latency_ms_single_test"] = 1e3 * sorted(lat)[len(lat) // 2]
+    else:
+        line["config"]["submission"] = "one synchronous etest_batch call per step (graph replay)"
     # this run's per-split statistics, read before the FP32 form below reuses the outputs
     host_ps = [ps.cpu().numpy()] if len(kinds) == 1 else [o.cpu().numpy() for o in outs]
     if wl.prec == "bf16r":
@@ -428,7 +431,8 @@ def run_batched(args):
                for a, b in zip(outs, seq_out))
     line = base_line(args, "ed_f32_batch256_B2000", value, elapsed, args.steps, "f32",
                      {"tests": len(tests), "B": 2000, "nx_ny_range": [50, 1500],
-                      "p": [20, 100, 500], "precision": "f32", "graph": True})
+                      "p": [20, 100, 500], "precision": "f32",
+                      "submission": "one synchronous etest_batch call per step (graph replay)"})
     line.update({"gram_tflops": gram_tf, "resampling_tflops": res_tf,
                  "stage_ms": {k: round(v, 5) for k, v in stage.items()}, "roofline": roof,
                  "sequential_ms_per_step": 1e3 * e_seq / seq_steps,

@@ -138,11 +138,11 @@ etest_status etest_run(const etest_request* req, void* stream, etest_result* out
 /* Enqueue one test on `stream` and return without waiting.  d_out is a device pointer to
    one etest_result, written by the pass's last kernel; it must stay valid until the stream
    has reached the end of the work.  Scratch memory: one workspace per (device, stream),
-   taken from the stream-ordered allocator on the first call and kept for the calls that
-   follow on that stream (they run in stream order, so each reuses it without waiting for
-   the previous one); a call that needs more replaces it, the old one being freed in
-   stream order.  The workspace is held until the process ends.  Under stream capture the
-   call allocates and frees its own workspace instead. */
+   allocated on the first call and kept for the calls that follow on that stream (they run
+   in stream order, so each reuses it without waiting for the previous one); a call that
+   needs more replaces it, which waits for the device once.  The workspace is held until
+   the process ends.  Under stream capture the call allocates and frees its own workspace
+   in stream order instead. */
 etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* stream);
 etest_status mmd_test_async(const etest_request* req, etest_result* d_out, void* stream);
 
@@ -254,11 +254,24 @@ etest_status etest_permutations(int64_t n, uint64_t seed, int64_t b0, int64_t co
 
 /* n independent tests in one batched pass: every stage is one launch covering all tests,
    and the launch sequence is captured once into a HIP graph and replayed while the same
-   request list (same bytes) and the same tuning rules come back; up to 4 graphs are kept,
-   each holding its workspace until evicted.  With stage timing on (etest_profile_enable)
+   request shapes, the same stream and the same tuning rules come back; up to 4 graphs are
+   kept (evicting one waits for the device), each holding its workspace until evicted.  With stage timing on (etest_profile_enable)
    the batch runs without a graph so that the stages can be timed.  outs: host array of n
    results.  Each test's result equals what etest_run gives for it alone. */
 etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, etest_result* outs);
+
+/* Asynchronous form of etest_batch: enqueue the n tests on `stream` and return without
+   waiting.  The pass is etest_batch's cached graph, replayed (eager, on the stream's
+   workspace as for ed_test_async, while stage timing is on or under stream capture).
+   d_outs: device array of n etest_result; test t's result is written there by its last
+   kernel, and the array must stay valid until the stream reaches the end of the work.
+   Each result equals what etest_run gives for the test alone.  A test whose X or Y holds
+   NaN or Inf gets NaN statistic and p-value in d_outs (the call has returned before the
+   device sees the data).  The descriptor tables go up from one of a few pinned staging
+   slots per host thread, each reused once its copy has run.  Errors: EINVAL (arguments),
+   ENOMEM, EDEVICE. */
+etest_status etest_batch_async(const etest_request* reqs, int64_t n, void* stream,
+                               etest_result* d_outs);
 
 /* ---- Stage-level calls (each step of the path, for parity checks) ---- */
 

@@ -69,6 +69,7 @@ SIGNATURES = [
     ("mmd_test_async", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("etest_run_async_noalloc", c_i32, [ctypes.POINTER(Request), c_vp, c_vp]),
     ("etest_batch", c_i32, [ctypes.POINTER(Request), c_i64, c_vp, ctypes.POINTER(Result)]),
+    ("etest_batch_async", c_i32, [ctypes.POINTER(Request), c_i64, c_vp, c_vp]),
     ("etest_membership", c_i32, [c_i64, c_i64, c_u64, c_i64, c_i64, c_vp, c_vp]),
     ("etest_blocks", c_i32, [ctypes.POINTER(Request), c_vp, c_vp, c_vp, c_vp]),
     ("etest_perm_stats_from_membership", c_i32, [ctypes.POINTER(Request), c_vp, c_i64, c_vp,

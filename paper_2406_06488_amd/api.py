@@ -232,6 +232,26 @@ def batch(requests, keep=None):
     return [dict(zip(_RESULT_KEYS, r)) for r in np.frombuffer(outs, dtype=dt).tolist()]
 
 
+def batch_async(requests, device="cuda"):
+    """Enqueue many tests in one batched pass on torch's current stream and return a
+    (n x 6) float64 device tensor of their etest_result records; read them with
+    results_from_device() after synchronising.  requests: a list of Request, or a ctypes
+    array of them."""
+    import torch
+    n = len(requests)
+    arr = requests if isinstance(requests, ctypes.Array) else (Request * n)(*requests)
+    out = torch.empty((n, 6), dtype=torch.float64, device=device)  # written by the library
+    check(_lib.load().etest_batch_async(arr, n, _stream(), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def results_from_device(buf):
+    """List of result dicts from the (n x 6) device tensor batch_async() returns."""
+    dt = np.dtype([(k, "<f8" if i < 3 else "<i8") for i, k in enumerate(_RESULT_KEYS)])
+    raw = buf.cpu().numpy().tobytes()
+    return [dict(zip(_RESULT_KEYS, r)) for r in np.frombuffer(raw, dtype=dt).tolist()]
+
+
 def membership(nx, ny, seed, b0, count, device="cuda"):
     """Splits b0..b0+count-1 as packed bits (count x ceil(n/32) int32 device tensor)."""
     import torch

@@ -418,10 +418,10 @@ static hipError_t stream_workspace(hipStream_t st, size_t total, void** out) {
       *out = c.ws;
       return hipSuccess;
     }
-    if (c.ws) (void)hipFreeAsync(c.ws, st);
+    if (c.ws) (void)hipFree(c.ws);  // waits for the device first: rare (growth only)
     c.ws = nullptr;
     c.bytes = 0;
-    e = hipMallocAsync(&c.ws, total, st);
+    e = hipMalloc(&c.ws, total);
     if (e != hipSuccess || !c.ws) {
       c.ws = nullptr;
       return e != hipSuccess ? e : hipErrorOutOfMemory;
@@ -431,11 +431,42 @@ static hipError_t stream_workspace(hipStream_t st, size_t total, void** out) {
     return hipSuccess;
   }
   void* w = nullptr;
-  e = hipMallocAsync(&w, total, st);
+  e = hipMalloc(&w, total);
   if (e != hipSuccess || !w) return e != hipSuccess ? e : hipErrorOutOfMemory;
   g_sws.push_back(StreamWorkspace{dev, st, w, total});
   *out = w;
   return hipSuccess;
+}
+
+// Pinned staging for the descriptor tables of asynchronous batches: a small ring per host
+// thread.  A slot is handed out again only once the copy from it has run (an event recorded
+// after the copy), so a caller can run a few calls ahead of the device.
+struct PinnedSlot {
+  void* buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+constexpr int PINNED_SLOTS = 4;
+static thread_local PinnedSlot g_pinned[PINNED_SLOTS];
+static thread_local int g_pinned_next = 0;
+
+static PinnedSlot* pinned_slot(size_t bytes) {
+  PinnedSlot& s = g_pinned[g_pinned_next];
+  g_pinned_next = (g_pinned_next + 1) % PINNED_SLOTS;
+  if (s.used && hipEventSynchronize(s.done) != hipSuccess) return nullptr;
+  s.used = false;
+  if (s.cap < bytes) {
+    if (s.buf) (void)hipHostFree(s.buf);
+    s.buf = nullptr;
+    s.cap = 0;
+    if (hipHostMalloc(&s.buf, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    s.cap = bytes;
+  }
+  if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableSystemFence |
+                                                      hipEventDisableTiming) != hipSuccess)
+    return nullptr;
+  return &s;
 }
 
 etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered) {
@@ -486,6 +517,16 @@ etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered) {
     // buffer has to outlive the call), and the same kernel clears the flag words
     launch_put_desc(b->descs[0], b->offs.data(), b->d_descs, b->d_offs, st);
     e = hipGetLastError();
+  } else if (b->desc_pinned) {
+    // descriptors and launch tables are adjacent on the device: one copy of both
+    PinnedSlot* slot = pinned_slot(desc_bytes + offs_bytes);
+    if (!slot) return set_error(ETEST_ENOMEM, "pinned staging slot");
+    char* h = (char*)slot->buf;
+    std::memcpy(h, b->descs.data(), sizeof(TestDesc) * (size_t)n);
+    std::memcpy(h + desc_bytes, b->offs.data(), sizeof(int64_t) * b->offs.size());
+    e = hipMemcpyAsync(b->d_descs, h, desc_bytes + offs_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(slot->done, st);
+    slot->used = e == hipSuccess;
   } else {
     e = hipMemcpyAsync(b->d_descs, b->descs.data(), sizeof(TestDesc) * (size_t)n,
                        hipMemcpyHostToDevice, st);
@@ -808,7 +849,7 @@ static ShapeKey shape_of(const etest_request& r, const Pairing& pg, int64_t t) {
 struct GraphEntry {
   std::vector<ShapeKey> key;
   uint64_t tune_gen = 0;  // tuning rules the captured work shapes came from
-
+  hipStream_t stream = nullptr;  // calls on one stream share the entry's workspace in order
   Batch batch;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -818,14 +859,16 @@ static std::list<GraphEntry> g_graphs;
 static const size_t kGraphCacheMax = 4;
 
 static bool same_shapes(const GraphEntry& g, const etest_request* b, int64_t n, uint64_t gen,
-                        const Pairing& pg) {
-  if (g.tune_gen != gen || (int64_t)g.key.size() != n) return false;
+                        const Pairing& pg, hipStream_t st) {
+  if (g.stream != st || g.tune_gen != gen || (int64_t)g.key.size() != n) return false;
   for (int64_t t = 0; t < n; ++t)
     if (!(g.key[(size_t)t] == shape_of(b[t], pg, t))) return false;
   return true;
 }
 
 static void destroy_entry(GraphEntry& g) {
+  // an asynchronous replay of it may still be queued
+  (void)hipDeviceSynchronize();
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (g.graph) (void)hipGraphDestroy(g.graph);
   free_batch(&g.batch, nullptr, false);
@@ -845,62 +888,77 @@ static TestDesc* pinned_descs(size_t n) {
   return buf;
 }
 
+// The cached graph of a request list on stream st, captured on first use (g_graph_mu held).
+static etest_status graph_entry(const etest_request* reqs, int64_t n, hipStream_t st,
+                                const Pairing& pairing, GraphEntry** out) {
+  const uint64_t gen = tune_generation();
+  for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+    if (same_shapes(*it, reqs, n, gen, pairing, st)) {
+      g_graphs.splice(g_graphs.begin(), g_graphs, it);
+      *out = &g_graphs.front();
+      return ETEST_OK;
+    }
+  GraphEntry g;
+  for (int64_t t = 0; t < n; ++t) g.key.push_back(shape_of(reqs[t], pairing, t));
+  g.tune_gen = gen;
+  g.stream = st;
+  etest_status s = build_batch(reqs, n, false, &g.batch);
+  if (s != ETEST_OK) return s;
+  // Workspace and tables are placed before capture; the graph holds kernels only.
+  s = place_batch(&g.batch, st, false);
+  if (s != ETEST_OK) {
+    free_batch(&g.batch, nullptr, false);
+    return s;
+  }
+  HIP_OK(hipStreamSynchronize(st), "descriptor copy");
+  hipStream_t cap = nullptr;
+  HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    enqueue_batch(g.batch, cap, nullptr, nullptr, thread_fork());
+    e = hipStreamEndCapture(cap, &g.graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    destroy_entry(g);
+    return set_error(ETEST_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  g_graphs.push_front(std::move(g));
+  while (g_graphs.size() > kGraphCacheMax) {
+    destroy_entry(g_graphs.back());
+    g_graphs.pop_back();
+  }
+  *out = &g_graphs.front();
+  return ETEST_OK;
+}
+
+// This call's pointers, seeds and gammas (and, asynchronous calls, result addresses) into
+// host descriptors for the entry's tables.
+static void fill_descs(const GraphEntry& g, const etest_request* reqs, int64_t n,
+                       const Pairing& pairing, TestDesc* hd, etest_result* d_outs) {
+  const Batch& b = g.batch;
+  for (int64_t t = 0; t < n; ++t) {
+    TestPlan P = make_plan(reqs[t]);
+    assign_pointers(P, (char*)b.ws + b.base[(size_t)t], b.d_results + t);
+    if (d_outs) P.d.out6 = (double*)(d_outs + t);
+    hd[t] = P.d;
+  }
+  link_partners(hd, pairing);
+}
+
 static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStream_t st,
                                     etest_result* outs) {
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  GraphEntry* hit = nullptr;
-  const uint64_t gen = tune_generation();
   const Pairing pairing = pair_tests(reqs, n);
-  for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
-    if (same_shapes(*it, reqs, n, gen, pairing)) {
-      g_graphs.splice(g_graphs.begin(), g_graphs, it);
-      hit = &g_graphs.front();
-      break;
-    }
-  if (!hit) {
-    GraphEntry g;
-    for (int64_t t = 0; t < n; ++t) g.key.push_back(shape_of(reqs[t], pairing, t));
-    g.tune_gen = gen;
-    etest_status s = build_batch(reqs, n, false, &g.batch);
-    if (s != ETEST_OK) return s;
-    // Workspace and tables are placed before capture; the graph holds kernels only.
-    s = place_batch(&g.batch, st, false);
-    if (s != ETEST_OK) {
-      free_batch(&g.batch, nullptr, false);
-      return s;
-    }
-    HIP_OK(hipStreamSynchronize(st), "descriptor copy");
-    hipStream_t cap = nullptr;
-    HIP_OK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      enqueue_batch(g.batch, cap, nullptr, nullptr, thread_fork());
-      e = hipStreamEndCapture(cap, &g.graph);
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) {
-      destroy_entry(g);
-      return set_error(ETEST_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    }
-    g_graphs.push_front(std::move(g));
-    hit = &g_graphs.front();
-    while (g_graphs.size() > kGraphCacheMax) {
-      destroy_entry(g_graphs.back());
-      g_graphs.pop_back();
-    }
-  }
-  // this call's pointers, seeds and gammas into the entry's descriptor table
+  GraphEntry* hit = nullptr;
+  etest_status s = graph_entry(reqs, n, st, pairing, &hit);
+  if (s != ETEST_OK) return s;
   Batch& b = hit->batch;
   TestDesc* hd = pinned_descs((size_t)n);
   DevResult* hr = pinned_results((size_t)n);
   if (!hd || !hr) return set_error(ETEST_ENOMEM, "pinned staging buffer");
-  for (int64_t t = 0; t < n; ++t) {
-    TestPlan P = make_plan(reqs[t]);
-    assign_pointers(P, (char*)b.ws + b.base[(size_t)t], b.d_results + t);
-    hd[t] = P.d;
-  }
-  link_partners(hd, pairing);
+  fill_descs(*hit, reqs, n, pairing, hd, nullptr);
   HIP_OK(hipMemcpyAsync(b.d_descs, hd, sizeof(TestDesc) * (size_t)n, hipMemcpyHostToDevice, st),
          "descriptor copy");
   HIP_OK(hipGraphLaunch(hit->exec, st), "graph launch");
@@ -915,6 +973,27 @@ static etest_status run_batch_graph(const etest_request* reqs, int64_t n, hipStr
     else if (worst == ETEST_OK) worst = r;
   }
   return worst;
+}
+
+// The graph replay without waiting: descriptors from a pinned staging slot (reused once its
+// copy has run), results written into d_outs by each test's last kernel.
+static etest_status enqueue_batch_graph(const etest_request* reqs, int64_t n, hipStream_t st,
+                                        etest_result* d_outs) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  const Pairing pairing = pair_tests(reqs, n);
+  GraphEntry* hit = nullptr;
+  etest_status s = graph_entry(reqs, n, st, pairing, &hit);
+  if (s != ETEST_OK) return s;
+  PinnedSlot* slot = pinned_slot(sizeof(TestDesc) * (size_t)n);
+  if (!slot) return set_error(ETEST_ENOMEM, "pinned staging slot");
+  fill_descs(*hit, reqs, n, pairing, (TestDesc*)slot->buf, d_outs);
+  HIP_OK(hipMemcpyAsync(hit->batch.d_descs, slot->buf, sizeof(TestDesc) * (size_t)n,
+                        hipMemcpyHostToDevice, st),
+         "descriptor copy");
+  HIP_OK(hipEventRecord(slot->done, st), "staging event");
+  slot->used = true;
+  HIP_OK(hipGraphLaunch(hit->exec, st), "graph launch");
+  return ETEST_OK;
 }
 
 }  // namespace et
@@ -1055,6 +1134,32 @@ static etest_status enqueue_async(const etest_request* req, int kind, etest_resu
   return ETEST_OK;
 }
 
+// n tests enqueued on the stream's cached workspace, one launch per stage over all of them,
+// without waiting; test t's result goes to d_outs[t] from its last kernel.
+static etest_status enqueue_batch_async(const etest_request* reqs, int64_t n,
+                                        etest_result* d_outs, void* stream) {
+  init_pool_once();
+  hipStream_t st = (hipStream_t)stream;
+  Batch b;
+  etest_status s = build_batch(reqs, n, false, &b);
+  if (s != ETEST_OK) return s;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const hipError_t ce = hipStreamIsCapturing(st, &cap);
+  if (ce != hipSuccess) (void)hipGetLastError();
+  b.cached = ce == hipSuccess && cap == hipStreamCaptureStatusNone;
+  // pinned staging does not suit a captured graph (the slot would be reused under it)
+  b.desc_by_kernel = n == 1;
+  b.desc_pinned = n > 1 && b.cached;
+  for (int64_t t = 0; t < n; ++t) b.plans[(size_t)t].d.out6 = (double*)(d_outs + t);
+  s = place_batch(&b, st, true);
+  if (s != ETEST_OK) return s;
+  enqueue_batch(b, st, nullptr, profile_events(), thread_fork());
+  free_batch(&b, st, true);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(ETEST_EDEVICE, std::string("enqueue: ") + hipGetErrorString(e));
+  return ETEST_OK;
+}
+
 etest_status ed_test_async(const etest_request* req, etest_result* d_out, void* stream) {
   return enqueue_async(req, ETEST_ED, d_out, stream);
 }
@@ -1073,6 +1178,24 @@ etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, ete
   // (events recorded by graph nodes give no elapsed times).
   if (g_prof.on) return run_device(reqs, n, (hipStream_t)stream, outs);
   return run_batch_graph(reqs, n, (hipStream_t)stream, outs);
+}
+
+etest_status etest_batch_async(const etest_request* reqs, int64_t n, void* stream,
+                               etest_result* d_outs) {
+  if (!reqs || !d_outs || n < 1)
+    return set_error(ETEST_EINVAL, "reqs/d_outs must be non-NULL, n >= 1");
+  for (int64_t t = 0; t < n; ++t) {
+    etest_status s = validate_request(reqs[t]);
+    if (s != ETEST_OK) return s;
+  }
+  // With stage timing on (events in graph nodes give no elapsed times) or under stream
+  // capture the pass is enqueued eagerly; otherwise the cached graph is replayed.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const hipError_t ce = hipStreamIsCapturing((hipStream_t)stream, &cap);
+  if (ce != hipSuccess) (void)hipGetLastError();
+  if (g_prof.on || ce != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return enqueue_batch_async(reqs, n, d_outs, stream);
+  return enqueue_batch_graph(reqs, n, (hipStream_t)stream, d_outs);
 }
 
 etest_status etest_membership(int64_t nx, int64_t ny, uint64_t seed, int64_t b0, int64_t count,

@@ -129,6 +129,9 @@ struct Batch {
   // single test: the descriptor and launch table go to the device as kernel arguments
   // (launch_put_desc, which also clears the flag words) instead of two host copies
   bool desc_by_kernel = false;
+  // several tests: descriptors and launch tables go up in one copy from a pinned staging
+  // slot (pinned_slot) instead of two copies from pageable host memory
+  bool desc_pinned = false;
 };
 
 // Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).

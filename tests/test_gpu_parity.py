@@ -407,6 +407,38 @@ def test_async_calls_back_to_back_reuse_the_stream_workspace():
         assert torch.equal(ps, s["perm_stats"]), k
 
 
+def test_batch_async_equals_batch():
+    """etest_batch_async runs the batched pass eagerly on the stream's workspace and writes
+    each result from the test's last kernel; called twice back to back (no synchronisation
+    between) it must equal etest_batch bit for bit, an ED / MMD pair sharing its Gram and a
+    lone test included."""
+    B = 500
+    specs = [(300, 170, 37, "f32", "ed", 91), (300, 170, 37, "f32", "mmd", 91),
+             (520, 480, 70, "bf16r", "ed", 92), (90, 110, 12, "f32", "ed", 93)]
+    data = {}
+    reqs, stats = [], []
+    for nx, ny, p, prec, kind, seed in specs:
+        if seed not in data:
+            X, Y = _data(nx, ny, p, seed, prec)
+            data[seed] = (_dev(X, prec), _dev(Y, prec))
+        Xd, Yd = data[seed]
+        ps = torch.zeros(B, dtype=torch.float64, device=DEV)
+        stats.append(ps)
+        reqs.append(api.make_request(Xd, Yd, B, seed + 7, kind, prec,
+                                     1.0 / p if kind == "mmd" else 0.0, ps))
+    say("batch_async", len(reqs), "tests")
+    first = api.batch_async(reqs)
+    second = api.batch_async(reqs)
+    torch.cuda.synchronize()
+    a1, a2 = api.results_from_device(first), api.results_from_device(second)
+    got = [t.clone() for t in stats]
+    ref = api.batch(reqs)
+    torch.cuda.synchronize()
+    assert a1 == ref and a2 == ref
+    for g, t in zip(got, stats):
+        assert torch.equal(g, t)
+
+
 # --------------------------------------------------------------------------- tuned shapes
 
 @pytest.mark.parametrize("prec,kc,cc", [("f32", 1, 1), ("f32", 5, 2), ("f32", 64, 2),
