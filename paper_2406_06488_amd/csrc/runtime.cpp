@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <list>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -401,40 +402,44 @@ void assign_pointers(TestPlan& P, char* r, DevResult* result) {
 struct StreamWorkspace {
   int dev;
   hipStream_t st;
-  void* ws;
-  size_t bytes;
+  std::mutex mu;  // held from placement until the pass is enqueued
+  void* ws = nullptr;
+  size_t bytes = 0;
 };
 static std::mutex g_sws_mu;
-static std::vector<StreamWorkspace> g_sws;
+static std::vector<std::unique_ptr<StreamWorkspace>> g_sws;
 
-static hipError_t stream_workspace(hipStream_t st, size_t total, void** out) {
+static hipError_t stream_workspace(hipStream_t st, size_t total, void** out,
+                                   std::unique_lock<std::mutex>* hold) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(g_sws_mu);
-  for (StreamWorkspace& c : g_sws) {
-    if (c.dev != dev || c.st != st) continue;
-    if (c.ws && c.bytes >= total) {
-      *out = c.ws;
-      return hipSuccess;
+  StreamWorkspace* c = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_sws_mu);
+    for (auto& p : g_sws)
+      if (p->dev == dev && p->st == st) c = p.get();
+    if (!c) {
+      g_sws.push_back(std::make_unique<StreamWorkspace>());
+      c = g_sws.back().get();
+      c->dev = dev;
+      c->st = st;
     }
-    if (c.ws) (void)hipFree(c.ws);  // waits for the device first: rare (growth only)
-    c.ws = nullptr;
-    c.bytes = 0;
-    e = hipMalloc(&c.ws, total);
-    if (e != hipSuccess || !c.ws) {
-      c.ws = nullptr;
+  }
+  std::unique_lock<std::mutex> lk(c->mu);
+  if (!c->ws || c->bytes < total) {
+    if (c->ws) (void)hipFree(c->ws);  // waits for the device first: rare (growth only)
+    c->ws = nullptr;
+    c->bytes = 0;
+    e = hipMalloc(&c->ws, total);
+    if (e != hipSuccess || !c->ws) {
+      c->ws = nullptr;
       return e != hipSuccess ? e : hipErrorOutOfMemory;
     }
-    c.bytes = total;
-    *out = c.ws;
-    return hipSuccess;
+    c->bytes = total;
   }
-  void* w = nullptr;
-  e = hipMalloc(&w, total);
-  if (e != hipSuccess || !w) return e != hipSuccess ? e : hipErrorOutOfMemory;
-  g_sws.push_back(StreamWorkspace{dev, st, w, total});
-  *out = w;
+  *out = c->ws;
+  *hold = std::move(lk);
   return hipSuccess;
 }
 
@@ -481,7 +486,7 @@ etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered) {
     total += b->plans[(size_t)t].bytes;
   }
   void* ws = nullptr;
-  hipError_t e = b->cached ? stream_workspace(st, total, &ws)
+  hipError_t e = b->cached ? stream_workspace(st, total, &ws, &b->ws_hold)
                  : stream_ordered ? hipMallocAsync(&ws, total, st)
                                   : hipMalloc(&ws, total);
   if (e != hipSuccess || !ws) {
@@ -539,6 +544,7 @@ etest_status place_batch(Batch* b, hipStream_t st, bool stream_ordered) {
 }
 
 void free_batch(Batch* b, hipStream_t st, bool stream_ordered) {
+  if (b->ws_hold.owns_lock()) b->ws_hold.unlock();
   if (b->ws && !b->cached) {
     if (stream_ordered) (void)hipFreeAsync(b->ws, st);
     else (void)hipFree(b->ws);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -126,6 +127,10 @@ struct Batch {
   // ws comes from the stream's cached workspace (stream_workspace) and is not freed with
   // the batch
   bool cached = false;
+  // held while a cached workspace's pass is enqueued, so that concurrent callers on one
+  // stream cannot interleave their launches over the same workspace (released by
+  // free_batch)
+  std::unique_lock<std::mutex> ws_hold;
   // single test: the descriptor and launch table go to the device as kernel arguments
   // (launch_put_desc, which also clears the flag words) instead of two host copies
   bool desc_by_kernel = false;

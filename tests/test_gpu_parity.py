@@ -407,6 +407,36 @@ def test_async_calls_back_to_back_reuse_the_stream_workspace():
         assert torch.equal(ps, s["perm_stats"]), k
 
 
+def test_async_calls_from_two_threads_on_one_stream():
+    """Two host threads enqueue asynchronous tests on the same (default) stream at once:
+    each pass holds the stream's workspace until all its launches are queued, so the
+    passes cannot interleave over it; every result must equal the synchronous call's."""
+    import threading
+    B = 400
+    X, Y = _data(400, 380, 40, 95, "f32")
+    Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+    torch.cuda.synchronize()
+    outs = {}
+
+    def worker(tag):
+        for k in range(4):
+            seed = 100 * tag + k
+            outs[seed] = api.run_async(Xd, Yd, B, seed, "ed", "f32")
+
+    say("two threads, one stream")
+    th = [threading.Thread(target=worker, args=(t,)) for t in (1, 2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    for seed, buf in sorted(outs.items()):
+        a = api.result_from_device(buf)
+        s = api.run(Xd, Yd, B, seed, "ed", "f32", with_perm_stats=False)
+        assert a["statistic"] == s["statistic"] and a["count_ge"] == s["count_ge"], seed
+        assert a["threshold"] == s["threshold"], seed
+
+
 def test_batch_async_equals_batch():
     """etest_batch_async runs the batched pass eagerly on the stream's workspace and writes
     each result from the test's last kernel; called twice back to back (no synchronisation
