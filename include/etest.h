@@ -268,8 +268,9 @@ etest_status etest_batch(const etest_request* reqs, int64_t n, void* stream, ete
    Each result equals what etest_run gives for the test alone.  A test whose X or Y holds
    NaN or Inf gets NaN statistic and p-value in d_outs (the call has returned before the
    device sees the data).  The descriptor tables go up from one of a few pinned staging
-   slots per host thread, each reused once its copy has run.  Errors: EINVAL (arguments),
-   ENOMEM, EDEVICE. */
+   slots per host thread, each reused once its copy has run.  Under stream capture only
+   n = 1 is accepted (its descriptor travels as kernel arguments).  Errors: EINVAL
+   (arguments; n > 1 under capture), ENOMEM, EDEVICE. */
 etest_status etest_batch_async(const etest_request* reqs, int64_t n, void* stream,
                                etest_result* d_outs);
 

@@ -1199,8 +1199,11 @@ etest_status etest_batch_async(const etest_request* reqs, int64_t n, void* strea
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   const hipError_t ce = hipStreamIsCapturing((hipStream_t)stream, &cap);
   if (ce != hipSuccess) (void)hipGetLastError();
-  if (g_prof.on || ce != hipSuccess || cap != hipStreamCaptureStatusNone)
-    return enqueue_batch_async(reqs, n, d_outs, stream);
+  const bool capturing = ce != hipSuccess || cap != hipStreamCaptureStatusNone;
+  // a captured copy would read the call's host tables after they are gone
+  if (capturing && n > 1)
+    return set_error(ETEST_EINVAL, "etest_batch_async takes one test under stream capture");
+  if (g_prof.on || capturing) return enqueue_batch_async(reqs, n, d_outs, stream);
   return enqueue_batch_graph(reqs, n, (hipStream_t)stream, d_outs);
 }
 
