@@ -394,10 +394,12 @@ void assign_pointers(TestPlan& P, char* r, DevResult* result) {
 
 // One device workspace per (device, stream) for the asynchronous entry points.  Calls on
 // one stream run in stream order, so each call can reuse the workspace of the previous one
-// without waiting for it; allocating and freeing a workspace per call instead made each
-// call wait on the host until the device had caught up with the previous call's free
-// (measured: 0.5 ms of host time per plain_f32 test, the whole step).  A call that needs
-// more than the cached size replaces it (the old one is freed in stream order).  The
+// without waiting for it.  (With a workspace allocated and freed per call, and descriptors
+// copied from pageable memory, each call instead waited on the host for the device: 0.5 ms
+// of host time per plain_f32 test, the whole step.)  A call that needs more than the
+// cached size replaces it with hipFree / hipMalloc, which wait for the device (growth
+// only).  The entry's lock is held from placement until the call's pass is enqueued, so
+// that two callers on one stream cannot interleave launches over the same memory.  The
 // memory stays held until the process ends.
 struct StreamWorkspace {
   int dev;
