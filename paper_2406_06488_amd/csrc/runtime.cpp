@@ -555,12 +555,14 @@ void free_batch(Batch* b, hipStream_t st, bool stream_ordered) {
 }
 
 // Split stream after the block stage once it has more workgroups than the chip holds at
-// once (8 per CU of MI355X's 256).  ETEST_SPLIT_LATE = 0 / 1 forces either order.
+// once (8 per CU of MI355X's 256), or when the block stage runs on super tiles, whose
+// workgroups take a CU's LDS and register file whole and leave the split stream no room
+// beside them.  ETEST_SPLIT_LATE = 0 / 1 forces either order.
 constexpr int64_t SPLIT_EARLY_MAX_WG = 8 * 256;
-static bool split_late(int64_t member_wg) {
+static bool split_late(int64_t member_wg, int64_t super_wg) {
   static const int env = env_int("ETEST_SPLIT_LATE", -1, -1, 1);
   if (env >= 0) return env == 1;
-  return member_wg > SPLIT_EARLY_MAX_WG;
+  return member_wg > SPLIT_EARLY_MAX_WG || super_wg > 0;
 }
 
 void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_offs, int n,
@@ -583,12 +585,13 @@ void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_o
   // Split stream: independent of the data, so it runs beside other stages.  A stream that
   // fits on the chip at once (up to SPLIT_EARLY_MAX_WG workgroups: each one's walk over the
   // pooled items is latency-bound) is forked after staging, a short memory-bound stage, and
-  // runs beside the block stage, whose grid leaves room on the CUs.  A larger one (many
-  // tests in one launch) keeps every CU's vector ALU busy for its whole duration and would
-  // slow the block stage by about as much as it overlaps; it is forked after the block stage
-  // and runs beside the sums and the centring, which are bound by memory.
+  // runs beside the 128-tile block stage, whose grid leaves room on the CUs.  A larger one
+  // (many tests in one launch) keeps every CU's vector ALU busy for its whole duration and
+  // would slow the block stage by about as much as it overlaps, and super-tile workgroups
+  // leave it no room; then it is forked after the block stage and runs beside the sums and
+  // the centring, which are bound by memory.
   hipStream_t ms = st;
-  const bool late = fork && split_late(total(S_MEMBER));
+  const bool late = fork && split_late(total(S_MEMBER), total(S_GRAM_F32S) + total(S_GRAM_BF16S));
   auto split = [&]() {
     if (fork) {
       (void)hipEventRecord(fork->start, st);
