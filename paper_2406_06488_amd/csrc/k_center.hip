@@ -50,6 +50,9 @@ __device__ inline uint32_t pack_h2(_Float16 a, _Float16 b) {
   return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
+// One workgroup per half tile (rows 64 rh .. + 63: fragment row blocks 2 rh and 2 rh + 1),
+// so that the grid has twice as many workgroups as stored tiles in flight; on grids
+// planned with one workgroup per tile (past 2^22 tiles) a workgroup takes both halves.
 __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict__ descs,
                                                       const int64_t* __restrict__ offs,
                                                       int ntests) {
@@ -57,7 +60,10 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
   __shared__ double crow[TILE], ccol[TILE];
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
-  const int t = (int)(blockIdx.x - offs[ti]);
+  const int64_t local = blockIdx.x - offs[ti];
+  const bool halves = offs[ti + 1] - offs[ti] > d.ntiles;  // two workgroups per tile
+  const int t = (int)(halves ? local >> 1 : local);
+  const int rh0 = halves ? (int)(local & 1) : 0, rh1 = halves ? rh0 + 1 : 2;
   int i, j;
   tile_coords(t, d.nt, &i, &j);
   const int rows_i = tile_rows(d, i), rows_j = tile_rows(d, j);
@@ -80,58 +86,61 @@ __global__ void __launch_bounds__(256) k_center_split(const TestDesc* __restrict
   uint8_t* P = (uint8_t*)d.planes + (int64_t)t * plane_bytes_per_entry(d.pfmt) * TILE * TILE;
   uint16_t* Phi = (uint16_t*)P;
   uint8_t* Plo = P + 2 * TILE * TILE;
-  // every load of the thread first (16 x 16 B in flight), then the conversions
-  constexpr int NQ = TILE * TILE / 8 / 256;
-  float4 raw[NQ][2];
+  for (int rh = rh0; rh < rh1; ++rh) {
+    // every load of the thread first (8 x 16 B in flight), then the conversions; fragment
+    // q of the half: 8 values of row block q / 512 (2 rh or 2 rh + 1)
+    constexpr int NQ = TILE * TILE / 8 / 256 / 2;
+    float4 raw[NQ][2];
 #pragma unroll
-  for (int it = 0; it < NQ; ++it) {
-    const int q = threadIdx.x + 256 * it;
-    const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
-    const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
-    raw[it][0] = *(const float4*)(Dt + r * TILE + c0l);
-    raw[it][1] = *(const float4*)(Dt + r * TILE + c0l + 4);
-  }
-#pragma unroll
-  for (int it = 0; it < NQ; ++it) {
-    const int q = threadIdx.x + 256 * it;
-    const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
-    const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
-    const float v[8] = {raw[it][0].x, raw[it][0].y, raw[it][0].z, raw[it][0].w,
-                        raw[it][1].x, raw[it][1].y, raw[it][1].z, raw[it][1].w};
-    const double ca = crow[r];
-    _Float16 hi[8], lo[8];
-    uint32_t lo8[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int col = c0l + e;
-      double x = 0.0;
-      if (r < rows_i && col < rows_j) x = ((((double)v[e] - ca) - ccol[col]) + c0) * half * scale;
-      // FP64 -> FP32 -> fp16 (both hardware conversions; a direct FP64 -> fp16 rounding is
-      // a long software sequence): hi may then round one way twice, which the low plane
-      // absorbs, since it is formed from the exact FP64 remainder x - hi
-      hi[e] = (_Float16)to_f32(x);
-      const double rem = x - (double)(float)hi[e];
-      if (f8lo) lo8[e] = f32_to_e4m3(to_f32(rem * 32.0));
-      else lo[e] = (_Float16)to_f32(rem * 2048.0);
+    for (int it = 0; it < NQ; ++it) {
+      const int q = rh * (NQ * 256) + threadIdx.x + 256 * it;
+      const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
+      const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
+      raw[it][0] = *(const float4*)(Dt + r * TILE + c0l);
+      raw[it][1] = *(const float4*)(Dt + r * TILE + c0l + 4);
     }
-    uint4 w;
-    w.x = pack_h2(hi[0], hi[1]); w.y = pack_h2(hi[2], hi[3]);
-    w.z = pack_h2(hi[4], hi[5]); w.w = pack_h2(hi[6], hi[7]);
-    *(uint4*)(Phi + (int64_t)q * 8) = w;
-    if (f8lo) {
-      // columns c0l .. c0l+7 are bytes (c0l % 16) .. +7 of half (c0l % 32) / 16 of lane
-      // (r % 32) + 32 ((c0l % 64) / 32) in fragment (mb, c0l / 64)
-      const int kb = c0l >> 6, g = (c0l >> 5) & 1, hf = (c0l >> 4) & 1;
-      const int64_t off = ((int64_t)((mb * 2 + kb) * 2 + hf) * 64 + (lane & 31) + 32 * g) * 16 +
-                          (c0l & 15);
-      uint2 b;
-      b.x = lo8[0] | (lo8[1] << 8) | (lo8[2] << 16) | (lo8[3] << 24);
-      b.y = lo8[4] | (lo8[5] << 8) | (lo8[6] << 16) | (lo8[7] << 24);
-      *(uint2*)(Plo + off) = b;
-    } else {
-      w.x = pack_h2(lo[0], lo[1]); w.y = pack_h2(lo[2], lo[3]);
-      w.z = pack_h2(lo[4], lo[5]); w.w = pack_h2(lo[6], lo[7]);
-      *(uint4*)(Phi + TILE * TILE + (int64_t)q * 8) = w;
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+      const int q = rh * (NQ * 256) + threadIdx.x + 256 * it;
+      const int mb = q >> 9, ks = (q >> 6) & 7, lane = q & 63;
+      const int r = mb * 32 + (lane & 31), c0l = ks * 16 + 8 * (lane >> 5);
+      const float v[8] = {raw[it][0].x, raw[it][0].y, raw[it][0].z, raw[it][0].w,
+                          raw[it][1].x, raw[it][1].y, raw[it][1].z, raw[it][1].w};
+      const double ca = crow[r];
+      _Float16 hi[8], lo[8];
+      uint32_t lo8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int col = c0l + e;
+        double x = 0.0;
+        if (r < rows_i && col < rows_j) x = ((((double)v[e] - ca) - ccol[col]) + c0) * half * scale;
+        // FP64 -> FP32 -> fp16 (both hardware conversions; a direct FP64 -> fp16 rounding is
+        // a long software sequence): hi may then round one way twice, which the low plane
+        // absorbs, since it is formed from the exact FP64 remainder x - hi
+        hi[e] = (_Float16)to_f32(x);
+        const double rem = x - (double)(float)hi[e];
+        if (f8lo) lo8[e] = f32_to_e4m3(to_f32(rem * 32.0));
+        else lo[e] = (_Float16)to_f32(rem * 2048.0);
+      }
+      uint4 w;
+      w.x = pack_h2(hi[0], hi[1]); w.y = pack_h2(hi[2], hi[3]);
+      w.z = pack_h2(hi[4], hi[5]); w.w = pack_h2(hi[6], hi[7]);
+      *(uint4*)(Phi + (int64_t)q * 8) = w;
+      if (f8lo) {
+        // columns c0l .. c0l+7 are bytes (c0l % 16) .. +7 of half (c0l % 32) / 16 of lane
+        // (r % 32) + 32 ((c0l % 64) / 32) in fragment (mb, c0l / 64)
+        const int kb = c0l >> 6, g = (c0l >> 5) & 1, hf = (c0l >> 4) & 1;
+        const int64_t off = ((int64_t)((mb * 2 + kb) * 2 + hf) * 64 + (lane & 31) + 32 * g) * 16 +
+                            (c0l & 15);
+        uint2 b;
+        b.x = lo8[0] | (lo8[1] << 8) | (lo8[2] << 16) | (lo8[3] << 24);
+        b.y = lo8[4] | (lo8[5] << 8) | (lo8[6] << 16) | (lo8[7] << 24);
+        *(uint2*)(Plo + off) = b;
+      } else {
+        w.x = pack_h2(lo[0], lo[1]); w.y = pack_h2(lo[2], lo[3]);
+        w.z = pack_h2(lo[4], lo[5]); w.w = pack_h2(lo[6], lo[7]);
+        *(uint4*)(Phi + TILE * TILE + (int64_t)q * 8) = w;
+      }
     }
   }
 }

@@ -251,7 +251,9 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   P.wg[S_MEMBER] = d.B_pad / MEMBER_SPLITS;
   P.wg[S_ROWSUM] = (2 * npad + 63) / 64;  // two threads per pooled position
   P.wg[S_CENTER_F64] = f64 ? d.ntiles : 0;
-  P.wg[S_CENTER_SPLIT] = f64 ? 0 : d.ntiles;
+  // one workgroup per half tile, or per tile on grids past 2^22 tiles (one dispatch holds
+  // fewer than 2^32 work-items)
+  P.wg[S_CENTER_SPLIT] = f64 ? 0 : (int64_t)d.ntiles * (d.ntiles <= (1 << 22) ? 2 : 1);
   const int64_t perm_wg = perm_units(d, (int)(d.B_pad / NP));
   P.wg[S_PERM_F64] = f64 ? perm_wg : 0;
   P.wg[S_PERM_S2] = d.pfmt == PLANES_F16_F16 ? perm_wg : 0;

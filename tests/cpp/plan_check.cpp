@@ -243,7 +243,8 @@ static void check_large_grids() {
       const bool supers = P.wg[S_GRAM_F32S] == st * (st + 1) / 2 && P.wg[S_GRAM_F32] == 0 &&
                           P.wg[S_GRAM_FIN] == nt * (nt + 1) / 2;
       CHECK(tiles || supers, "gram grid of nt = %lld", (long long)nt);
-      CHECK(P.wg[S_CENTER_SPLIT] == nt * (nt + 1) / 2, "centring grid of nt = %lld",
+      const int64_t ntl = nt * (nt + 1) / 2;  // stored tiles: two workgroups each up to 2^22
+      CHECK(P.wg[S_CENTER_SPLIT] == ntl * (ntl <= (1 << 22) ? 2 : 1), "centring grid of nt = %lld",
             (long long)nt);
     }
   }
