@@ -34,6 +34,7 @@ constexpr int NP = 256;              // split columns per resampling chunk
 constexpr int MAX_CC = 8;            // chunks per resampling workgroup, at most
 constexpr int COLSUM_ROWS = 32;      // pooled rows per partial column sum
 constexpr int MEMBER_SPLITS = 16;    // split columns per split-stream workgroup
+constexpr int MEMBER_SPLITS_WIDE = 32;  // the same for split streams larger than the chip
 constexpr int FLAG_COUNT = 4;        // int32 index of the 64-bit (count, finished WGs) word
 constexpr int FLAG_WORDS = 8;
 constexpr int FLAG_XMAX = 6;         // FP32 form: bits of max |input| (a non-negative float)

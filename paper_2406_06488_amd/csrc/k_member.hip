@@ -55,20 +55,22 @@ struct SplitDraw {
 // Internal layout Z[w][col]: columns 0..B-1 drawn splits, B the identity split,
 // the rest zero; words cover padded pooled positions (X tiles, then Y tiles).
 //
-// One workgroup serves MEMBER_SPLITS consecutive split columns and walks the pooled
+// One workgroup serves MSPL consecutive split columns and walks the pooled
 // tiles in order (one tile = 128 padded positions = 4 words).  The scaled draws
 // v_t = floor(u_t (n - t) / 2^64) do not depend on the running count, so waves 1..3
 // produce the next tile's draws into LDS while wave 0 runs the selection scan (one
 // lane per split) over the current one.  Positions without an item (tile padding)
 // hold v = 0xFFFFFFFF, which is never below need (< 2^31), so the scan is the same
 // branch-free step for every position and writes whole words.
-constexpr int MSPL = MEMBER_SPLITS;
-
 __device__ inline uint32_t scaled_draw(uint32_t lo, uint32_t hi, uint32_t m) {
   const uint64_t p_lo = (uint64_t)lo * m, p_hi = (uint64_t)hi * m;
   return (uint32_t)((p_hi + (p_lo >> 32)) >> 32);  // floor(u * m / 2^64), u = hi:lo
 }
 
+// MSPL is MEMBER_SPLITS, or MEMBER_SPLITS_WIDE for a launch with more workgroups than the
+// chip holds at once: there the stream is bound by vector-ALU cycles, and a wider
+// workgroup keeps twice as many of the scanning wave's lanes busy.
+template <int MSPL>
 __global__ void __launch_bounds__(MTHREADS) k_member(const TestDesc* __restrict__ descs,
                                                 const int64_t* __restrict__ offs, int ntests) {
   __shared__ uint32_t V[2][TILE][MSPL];
@@ -181,9 +183,11 @@ __global__ void __launch_bounds__(256) k_member_public(int64_t nx, int64_t ny, u
 }
 
 // blocks: B_pad / MEMBER_SPLITS workgroups per test
-void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n) {
+void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n,
+                   bool wide) {
   if (blocks > 0)
-    hipLaunchKernelGGL(k_member, dim3((unsigned)blocks), dim3(MTHREADS), 0, st, d, offs, n);
+    hipLaunchKernelGGL(wide ? k_member<MEMBER_SPLITS_WIDE> : k_member<MEMBER_SPLITS>,
+                       dim3((unsigned)blocks), dim3(MTHREADS), 0, st, d, offs, n);
 }
 void launch_member_public(int64_t nx, int64_t ny, uint64_t seed, int64_t b0, int64_t count,
                           uint32_t* words, hipStream_t st) {

@@ -27,7 +27,9 @@ void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int6
 void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
 void launch_center(bool f64, int64_t blocks, hipStream_t st, const TestDesc* d,
                    const int64_t* offs, int n);
-void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n);
+// wide: MEMBER_SPLITS_WIDE split columns per workgroup (the launch table must count them so)
+void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n,
+                   bool wide = false);
 void launch_member_public(int64_t nx, int64_t ny, uint64_t seed, int64_t b0, int64_t count,
                           uint32_t* words, hipStream_t st);
 void launch_member_import(int64_t bpad, hipStream_t st, const TestDesc* d, const uint32_t* w);
@@ -137,6 +139,8 @@ struct Batch {
   // several tests: descriptors and launch tables go up in one copy from a pinned staging
   // slot (pinned_slot) instead of two copies from pageable host memory
   bool desc_pinned = false;
+  // split stream of MEMBER_SPLITS_WIDE columns per workgroup (build_batch decides)
+  bool member_wide = false;
 };
 
 // Device address and size of this GPU's no-allocation scratch array (k_noalloc.hip).
@@ -183,7 +187,8 @@ struct Fork {
 // clear_flags false: the flag words were cleared already (launch_put_desc).
 void enqueue_stages(const TestDesc* D, const int64_t* d_offs, const int64_t* h_offs, int n,
                     bool dual, hipStream_t st, const uint32_t* import_words, int64_t import_bpad,
-                    const StageEvents* ev, const Fork* fork, bool clear_flags = true);
+                    const StageEvents* ev, const Fork* fork, bool clear_flags = true,
+                    bool member_wide = false);
 // Enqueue every stage.  import_words: caller splits for a single test (or null).
 void enqueue_batch(const Batch& b, hipStream_t st, const uint32_t* import_words = nullptr,
                    const StageEvents* events = nullptr, const Fork* fork = nullptr);

@@ -18,7 +18,7 @@ void launch_gram_finish(int64_t, hipStream_t, const TestDesc*, const int64_t*, i
 void launch_rowsum(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_observed(hipStream_t, const TestDesc*, const int64_t*, int) {}
 void launch_center(bool, int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
-void launch_member(int64_t, hipStream_t, const TestDesc*, const int64_t*, int) {}
+void launch_member(int64_t, hipStream_t, const TestDesc*, const int64_t*, int, bool) {}
 void launch_member_public(int64_t, int64_t, uint64_t, int64_t, int64_t, uint32_t*, hipStream_t) {}
 void launch_member_import(int64_t, hipStream_t, const TestDesc*, const uint32_t*) {}
 void launch_perm(int, int64_t, hipStream_t, const TestDesc*, const int64_t*, int, const int32_t*) {}
@@ -274,7 +274,43 @@ static void check_large_grids() {
   }
 }
 
+// Split-stream width: 16 splits per workgroup for a launch the chip holds at once, 32 for a
+// larger one, with every test's grid share counted in that width.
+static void check_member_width() {
+  auto req = [](int64_t nx, int64_t ny, int64_t B, const void* x) {
+    etest_request r{};
+    r.kind = ETEST_ED;
+    r.prec = ETEST_PREC_F32;
+    r.nx = nx;
+    r.ny = ny;
+    r.p = 100;
+    r.B = B;
+    r.seed = 3;
+    r.X = x;
+    r.Y = (const char*)x + 0x100000;
+    return r;
+  };
+  {
+    Batch b;
+    const etest_request r = req(2000, 2000, 10000, (const void*)0x1000);
+    CHECK(build_batch(&r, 1, false, &b) == ETEST_OK, "one test");
+    CHECK(!b.member_wide && b.plans[0].wg[S_MEMBER] == b.plans[0].d.B_pad / MEMBER_SPLITS,
+          "one test of B = 10^4: %lld split workgroups", (long long)b.plans[0].wg[S_MEMBER]);
+  }
+  {
+    std::vector<etest_request> rs;
+    for (int t = 0; t < 256; ++t) rs.push_back(req(50 + 5 * t, 1500 - 5 * t, 2000, (const void*)(uintptr_t)(0x1000000 * (t + 1))));
+    Batch b;
+    CHECK(build_batch(rs.data(), (int64_t)rs.size(), false, &b) == ETEST_OK, "256 tests");
+    CHECK(b.member_wide, "256 tests of B = 2000: narrow split stream");
+    for (const TestPlan& P : b.plans)
+      CHECK(P.wg[S_MEMBER] == P.d.B_pad / MEMBER_SPLITS_WIDE, "wide share %lld of B_pad %lld",
+            (long long)P.wg[S_MEMBER], (long long)P.d.B_pad);
+  }
+}
+
 int main() {
+  check_member_width();
   check_row_units();
   check_large_grids();
   const int precs[3] = {ETEST_PREC_F64, ETEST_PREC_F32, ETEST_PREC_BF16_REFINED};
