@@ -348,8 +348,6 @@ etest_status check_launch_sizes(const TestPlan* plans, size_t n) {
 // the memory-bound stages beside it (the batched workload of 256 tests: 6.53-6.60 ->
 // 6.36-6.37 ms per step).  Smaller streams keep 16: they are latency-bound walks, and
 // halving their workgroup count would leave CUs idle.
-constexpr int64_t MEMBER_WIDE_MIN_WG = 8 * 256;
-
 etest_status build_batch(const etest_request* reqs, int64_t n, bool internal_perm, Batch* b) {
   b->plans.clear();
   b->member_wide = false;

@@ -27,6 +27,9 @@ void launch_rowsum(int64_t blocks, hipStream_t st, const TestDesc* d, const int6
 void launch_observed(hipStream_t st, const TestDesc* d, const int64_t* sel, int n);
 void launch_center(bool f64, int64_t blocks, hipStream_t st, const TestDesc* d,
                    const int64_t* offs, int n);
+// A split-stream launch of more workgroups than MI355X holds at once (8 per CU of 256) at
+// MEMBER_SPLITS per workgroup runs MEMBER_SPLITS_WIDE per workgroup instead.
+constexpr int64_t MEMBER_WIDE_MIN_WG = 8 * 256;
 // wide: MEMBER_SPLITS_WIDE split columns per workgroup (the launch table must count them so)
 void launch_member(int64_t blocks, hipStream_t st, const TestDesc* d, const int64_t* offs, int n,
                    bool wide = false);

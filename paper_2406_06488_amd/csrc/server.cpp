@@ -379,6 +379,14 @@ void run_scheduler(etest_server* S) {
     int nres = 0;
     for (int k = 0; k < R; ++k) nres += S->slots[(size_t)k] ? 1 : 0;
     const double share = nres > 0 ? (double)S->cfg.chunk_updates / nres : 0.0;
+    // the split streams of this round's fresh requests: 32 splits per workgroup once they
+    // outgrow the chip, as in build_batch (the split words are the same either way)
+    int64_t member_wg = 0;
+    for (int k = 0; k < R; ++k) {
+      const Req* q = S->slots[(size_t)k];
+      if (q && q->front_pending) member_wg += q->plan.wg[S_MEMBER];
+    }
+    const bool member_wide = member_wg > MEMBER_WIDE_MIN_WG;
     bool any = false;
     for (int k = 0; k < R; ++k) {
       Req* q = S->slots[(size_t)k];
@@ -390,6 +398,7 @@ void run_scheduler(etest_server* S) {
                         S_CENTER_SPLIT})
             w[s] = P.wg[s];
           for (int s : GRAM_SLOTS) w[s] = P.wg[s];
+          if (member_wide && P.wg[S_MEMBER] > 0) w[S_MEMBER] = P.d.B_pad / MEMBER_SPLITS_WIDE;
           w[SEL_FRONT] = 1;
         }
         const int left = q->pc_total - q->pc_done;
@@ -432,7 +441,7 @@ void run_scheduler(etest_server* S) {
         launch_colmean(total(S_COLMEAN), st, D, offs(S_COLMEAN), R);
         launch_stage(total(S_STAGE), st, D, offs(S_STAGE), R);
         launch_gram_slots(offs, total, st, D, R, false);
-        launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), R);
+        launch_member(total(S_MEMBER), st, D, offs(S_MEMBER), R, member_wide);
         launch_rowsum(total(S_ROWSUM), st, D, offs(S_ROWSUM), R);
         launch_observed(st, D, offs(SEL_FRONT), R);
         launch_center(true, total(S_CENTER_F64), st, D, offs(S_CENTER_F64), R);
