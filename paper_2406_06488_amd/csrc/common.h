@@ -196,6 +196,28 @@ __device__ inline int64_t xcd_grouped(int64_t bid, int64_t grid) {
   return ((k / XCD_GROUP) * NUM_XCD + x) * XCD_GROUP + k % XCD_GROUP;
 }
 
+// Staging grids.  Partial column sums: one thread per (row chunk, column); for p < 256 a
+// 256-thread workgroup covers 256 / p row chunks of all p columns (otherwise most of its
+// threads would idle at small p), for p >= 256 one row chunk of 256 columns.
+__host__ __device__ inline int colpart_chunks_per_wg(int64_t p) {
+  return p >= 256 ? 1 : (int)(256 / p);
+}
+__host__ __device__ inline int64_t colpart_wgs(int64_t nrowchunks, int64_t p) {
+  const int c = colpart_chunks_per_wg(p);
+  return p >= 256 ? nrowchunks * ((p + 255) / 256) : (nrowchunks + c - 1) / c;
+}
+// Operand staging: the lanes that stage one padded row, the power of two covering p_pad / 4
+// (four columns per lane) up to a whole wave, so that a wave stages 64 / that many rows.
+__host__ __device__ inline int stage_lanes_per_row(int64_t p_pad) {
+  int l = 1;
+  while (l < 64 && 4 * l < p_pad) l <<= 1;
+  return l;
+}
+__host__ __device__ inline int64_t stage_wgs(int64_t npad, int64_t p_pad) {
+  const int64_t rows = 4 * (64 / stage_lanes_per_row(p_pad));  // per 4-wave workgroup
+  return (npad + rows - 1) / rows;
+}
+
 // Which test a flattened workgroup index belongs to: offs[t] <= bid < offs[t+1].
 __device__ inline int find_test(const int64_t* __restrict__ offs, int ntests, int64_t bid) {
   int lo = 0, hi = ntests - 1;

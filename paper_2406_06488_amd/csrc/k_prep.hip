@@ -27,10 +27,20 @@ __global__ void __launch_bounds__(256) k_colpart(const TestDesc* __restrict__ de
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
   const int64_t local = blockIdx.x - offs[ti];
-  const int ncb = (d.p + 255) / 256;
-  const int rc = (int)(local / ncb);
-  const int k = (int)(local % ncb) * 256 + threadIdx.x;
-  const bool ok = k < d.p;
+  const int cpw = colpart_chunks_per_wg(d.p);
+  int rc, k;
+  bool ok;
+  if (cpw > 1) {  // p < 256: row chunks local * cpw + threadIdx.x / p, all p columns
+    const int sub = (int)threadIdx.x / d.p;
+    k = (int)threadIdx.x % d.p;
+    rc = (int)(local * cpw) + sub;
+    ok = sub < cpw && rc < d.nrowchunks;
+  } else {
+    const int ncb = (d.p + 255) / 256;
+    rc = (int)(local / ncb);
+    k = (int)(local % ncb) * 256 + threadIdx.x;
+    ok = k < d.p;
+  }
   const int64_t n = (int64_t)d.nx + d.ny;
   const int64_t t0 = (int64_t)rc * ROWCHUNK;
   float v[ROWCHUNK];
@@ -80,11 +90,6 @@ __global__ void __launch_bounds__(64 * CM_GROUPS) k_colmean(const TestDesc* __re
   }
 }
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // fp16-pair operands: w -> (hi, lo) with hi = fp16(w 2^e), lo = fp16(w 2^e - hi), returned
 // packed (hi in the low half; the staging writes them to two planes); *r = (hi + lo) 2^-e, the value the Gram's products see (its norm goes to nrm, so
 // that |a|^2 + |b|^2 - 2 g is formed from one set of operand values).
@@ -97,14 +102,23 @@ __device__ inline uint32_t f16_pair(float w, int e, double* r) {
          ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
 }
 
-// One wave per padded pooled row: write W[pos][0..p_pad), nrm[pos]; flag NaN/Inf.
+// Sum over the lpr lanes (a power of two) that stage one row.
+__device__ inline double row_sum(double v, int lpr) {
+  for (int off = lpr >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// lpr = stage_lanes_per_row(p_pad) lanes per padded pooled row (a whole wave from
+// p_pad = 256 on): write W[pos][0..p_pad), nrm[pos]; flag NaN/Inf.
 __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ descs,
                                                const int64_t* __restrict__ offs, int ntests) {
   const int ti = find_test(offs, ntests, blockIdx.x);
   const TestDesc d = descs[ti];
   const int64_t local = blockIdx.x - offs[ti];
-  const int lane = threadIdx.x & 63;
-  const int64_t pos = local * 4 + (threadIdx.x >> 6);
+  const int lpr = stage_lanes_per_row(d.p_pad);
+  const int lane = (threadIdx.x & 63) & (lpr - 1);  // lane within the row's group
+  const int64_t pos = (local * 4 + (threadIdx.x >> 6)) * (64 / lpr) + (threadIdx.x & 63) / lpr;
+  const bool live = pos < (int64_t)d.nt * TILE;
   const int64_t split = (int64_t)d.tx * TILE;
   int64_t t = -1;  // pooled input row, -1 for padding
   if (pos < split) {
@@ -117,17 +131,17 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
   double nrm = 0.0;
   if (d.gop == GOP_F64) {
     double* W = (double*)d.W + pos * d.p_pad;
-    for (int k = lane; k < d.p_pad; k += 64) {
+    for (int k = lane; k < d.p_pad; k += lpr) {
       double v = 0.0;
       if (t >= 0 && k < d.p) {
         v = load_in_f64(d, t, k);
         bad |= !isfinite(v);
       }
-      W[k] = v;
+      if (live) W[k] = v;
       nrm += v * v;
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) ((double*)d.nrm)[pos] = nrm;
+    nrm = row_sum(nrm, lpr);
+    if (lane == 0 && live) ((double*)d.nrm)[pos] = nrm;
   } else {
     const bool bf = d.gop == GOP_BF16;
     const int e = bf ? 0 : f16_split_exponent(d);
@@ -139,7 +153,7 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
     // four columns per lane when every row starts on a 16-byte boundary
     const bool vec = (d.p & 3) == 0 && (((uintptr_t)d.X | (uintptr_t)d.Y) & 15) == 0;
     if (vec) {
-      for (int k = 4 * lane; k < d.p_pad; k += 256) {
+      for (int k = 4 * lane; k < d.p_pad; k += 4 * lpr) {
         float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (src && k < d.p) {
           const float4 x = *(const float4*)(src + k);
@@ -155,7 +169,7 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
           uint2 o;
           o.x = (uint32_t)h0 | ((uint32_t)h1 << 16);
           o.y = (uint32_t)h2 | ((uint32_t)h3 << 16);
-          *(uint2*)(Wu + blocked_index(pos, k >> 5, k & 31, nch)) = o;
+          if (live) *(uint2*)(Wu + blocked_index(pos, k >> 5, k & 31, nch)) = o;
           const double r0 = bf16_to_f32(h0), r1 = bf16_to_f32(h1);
           const double r2 = bf16_to_f32(h2), r3 = bf16_to_f32(h3);
           nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
@@ -169,13 +183,15 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
           lo.x = (q0 >> 16) | (q1 & 0xFFFF0000u);
           lo.y = (q2 >> 16) | (q3 & 0xFFFF0000u);
           uint16_t* wp = Wu + blocked_index(pos, k >> 4, k & 15, nch);
-          *(uint2*)wp = hi;
-          *(uint2*)(wp + 16) = lo;
+          if (live) {
+            *(uint2*)wp = hi;
+            *(uint2*)(wp + 16) = lo;
+          }
           nrm += ((r0 * r0 + r1 * r1) + r2 * r2) + r3 * r3;
         }
       }
     } else {
-      for (int k = lane; k < d.p_pad; k += 64) {
+      for (int k = lane; k < d.p_pad; k += lpr) {
         float v = 0.0f;
         if (src && k < d.p) {
           const float x = src[k];
@@ -184,21 +200,23 @@ __global__ void __launch_bounds__(256) k_stage(const TestDesc* __restrict__ desc
         }
         if (bf) {
           const uint16_t h = f32_to_bf16_rn(v);
-          Wu[blocked_index(pos, k >> 5, k & 31, nch)] = h;
+          if (live) Wu[blocked_index(pos, k >> 5, k & 31, nch)] = h;
           const float r = bf16_to_f32(h);
           nrm += (double)r * (double)r;
         } else {
           double r;
           const uint32_t q = f16_pair(v, e, &r);
           uint16_t* wp = Wu + blocked_index(pos, k >> 4, k & 15, nch);
-          wp[0] = (uint16_t)(q & 0xFFFFu);
-          wp[16] = (uint16_t)(q >> 16);
+          if (live) {
+            wp[0] = (uint16_t)(q & 0xFFFFu);
+            wp[16] = (uint16_t)(q >> 16);
+          }
           nrm += r * r;
         }
       }
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) ((float*)d.nrm)[pos] = (float)nrm;
+    nrm = row_sum(nrm, lpr);
+    if (lane == 0 && live) ((float*)d.nrm)[pos] = (float)nrm;
   }
   if (bad) {
     atomicOr(&d.flags[0], 1);

@@ -236,9 +236,9 @@ TestPlan make_plan(const etest_request& r, int64_t kc_override, int mode) {
   P.internal_perm = false;  // build_batch appends an internal output buffer when asked
 
   const bool f32like = !f64;
-  P.wg[S_COLPART] = f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0;
+  P.wg[S_COLPART] = f32like ? colpart_wgs(d.nrowchunks, r.p) : 0;
   P.wg[S_COLMEAN] = f32like ? (r.p + 63) / 64 : 0;
-  P.wg[S_STAGE] = npad / 4;
+  P.wg[S_STAGE] = stage_wgs(npad, d.p_pad);
   // the dense grid keeps one 128-tile workgroup per tile
   d.gshape = d.dense ? GSHAPE_TILE : gram_shape(r, d.nt);
   const bool sup = d.gshape == GSHAPE_SUPER;
@@ -1364,8 +1364,8 @@ etest_status etest_cross(const etest_request* req, void* stream, etest_cross_res
   d.flags = (int32_t*)(w + off[C_FLAGS]);
   // launch tables [0, workgroups] of the stages (a one-test batch)
   const bool f32like = !f64;
-  const int64_t wg[5] = {f32like ? (int64_t)d.nrowchunks * ((r.p + 255) / 256) : 0,
-                         f32like ? (r.p + 63) / 64 : 0, npad / 4, gram_wg, 0};
+  const int64_t wg[5] = {f32like ? colpart_wgs(d.nrowchunks, r.p) : 0,
+                         f32like ? (r.p + 63) / 64 : 0, stage_wgs(npad, d.p_pad), gram_wg, 0};
   int64_t hoffs[10];
   for (int k = 0; k < 5; ++k) {
     hoffs[2 * k] = 0;
