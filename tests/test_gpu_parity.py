@@ -292,6 +292,34 @@ def test_batch_equals_alone():
             assert torch.equal(keep[3 * t + 2], alone[t]["perm_stats"]), (rep, t)
 
 
+def test_wide_split_stream_equals_narrow():
+    """A batch whose split stream outgrows the chip runs it 32 splits per workgroup instead of
+    16: the split words, and so every result, are those of the same test run alone (narrow),
+    and the large test that tips the batch over matches the oracle."""
+    big = (60, 50, 8, 40000, 301)   # nx, ny, p, B, seed: 40 000 splits, 2 501 workgroups at 16
+    small = (100, 80, 12, 999, 302)
+    runs = []
+    for nx, ny, p, B, seed in (big, small):
+        X, Y = _data(nx, ny, p, seed, "f32")
+        Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+        runs.append((X, Y, Xd, Yd, B, seed, torch.zeros(B, dtype=torch.float64, device=DEV)))
+    reqs = [api.make_request(Xd, Yd, B, seed + 100, "ed", "f32", 0.0, ps)
+            for _, _, Xd, Yd, B, seed, ps in runs]
+    say("wide split stream: batch of B = %d and B = %d" % (big[3], small[3]))
+    outs = api.batch(reqs)
+    torch.cuda.synchronize()
+    X, Y, Xd, Yd, B, seed, ps = runs[1]
+    alone = api.run(Xd, Yd, B, seed + 100, "ed", "f32", 0.0)
+    for k in ("statistic", "threshold", "count_ge", "p_value"):
+        assert outs[1][k] == alone[k], k
+    assert torch.equal(ps, alone["perm_stats"])
+    X, Y, Xd, Yd, B, seed, ps = runs[0]
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), B, seed + 100)
+    g = dict(outs[0])
+    g["perm_stats"] = ps
+    compare_run(g, o, "f32", "wide split stream")
+
+
 @pytest.mark.parametrize("prec,p", [("f32", 70), ("bf16r", 70), ("f32", 1030)])
 def test_shared_block_stage_equals_alone(prec, p):
     """An ED and an MMD test on the same X, Y in one batch share staging and Gram (the ED
