@@ -379,7 +379,7 @@ void run_scheduler(etest_server* S) {
     int nres = 0;
     for (int k = 0; k < R; ++k) nres += S->slots[(size_t)k] ? 1 : 0;
     const double share = nres > 0 ? (double)S->cfg.chunk_updates / nres : 0.0;
-    // the split streams of this round's fresh requests: 32 splits per workgroup once they
+    // the split streams of this step's fresh requests: 32 splits per workgroup once they
     // outgrow the chip, as in build_batch (the split words are the same either way)
     int64_t member_wg = 0;
     for (int k = 0; k < R; ++k) {

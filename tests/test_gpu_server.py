@@ -29,7 +29,7 @@ SPECS = [(300, 200, 40, 1000, "ed", "bf16r"), (120, 150, 300, 2000, "mmd", "bf16
          (50, 60, 20, 1000, "ed", "f32"), (700, 500, 64, 3000, "mmd", "f32"),
          (100, 100, 10, 500, "ed", "f64"), (1200, 900, 128, 1000, "ed", "bf16r"),
          (64, 65, 7, 300, "mmd", "f64"), (400, 410, 96, 10000, "ed", "bf16r"),
-         # 40 000 splits: a round that admits it runs its split streams 32 per workgroup
+         # 40 000 splits: a serving step that admits it runs its split streams 32 per workgroup
          (80, 70, 12, 40000, "ed", "f32")]
 
 
