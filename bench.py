@@ -14,8 +14,9 @@ Workloads (--workload):
                   Gaussian MMD (sigma^2 = p), BF16-refined form, B = 10^4; the FP32 form of
                   the same tests is timed beside it
   batched         256 independent ED tests (nx, ny in [50, 1500], p in {20, 100, 500},
-                  B = 2000) in one graph-captured batch; tuned work shapes; the same tests
-                  run one by one are timed beside it
+                  B = 2000) in one graph-captured batch; work shapes tuned on the batch
+                  itself; the same tests run one by one (the library's shapes for a lone
+                  test) are timed beside it
   serving         Poisson stream of tests (200/s by default) through the continuous-batching
                   server; latency p50 / p99 and served tests per second
   cross_f32/_bf16 cross-ED test (permutation-free) on the plain_f32 / precision_bf16 data
@@ -404,18 +405,21 @@ def run_batched(args):
         data.append((X, Y))
         keep += [Xd, Yd]
         reqs.append(api.make_request(Xd, Yd, w.B, w.perm_seed, "ed", w.prec))
-    # tune the resampling work shape per size bucket on representative tests
-    buckets = []
-    for lo, hi in ((0, 1024), (1024, 2048), (2048, 1 << 31)):
-        idx = [i for i, w in enumerate(tests) if lo <= w.nx + w.ny < hi]
-        if not idx:
-            continue
-        i = idx[len(idx) // 2]
-        buckets.append({"prec": "f32", "n_lo": lo, "n_hi": hi, "X": keep[2 * i],
-                        "Y": keep[2 * i + 1], "B": tests[i].B, "kind": "ed"})
-    rules = autotune.tune(buckets, reps=2, log=log)
-    log("tuned:", [(r["n_lo"], r["n_hi"], r["kc"], r["cc"]) for r in rules])
     reqs = (api.Request * len(reqs))(*reqs)  # built once, passed as it is every step
+    # the same tests one by one (plain path), timed first, under the library's own shapes
+    # for a lone test (row units short enough that each test spreads over the chip)
+    seq_steps = max(1, args.steps // 4)
+
+    def seq():
+        return [api.run(keep[2 * i], keep[2 * i + 1], w.B, w.perm_seed, "ed", w.prec,
+                        with_perm_stats=False) for i, w in enumerate(tests)]
+    autotune.clear()
+    e_seq, _, _, _ = timed(seq, seq_steps, 1, profile=False)
+    # tune the resampling work shape per size bucket on the batch itself
+    ranges = [(lo, hi) for lo, hi in ((0, 1024), (1024, 2048), (2048, 1 << 31))
+              if any(lo <= w.nx + w.ny < hi for w in tests)]
+    rules = autotune.tune_batch(lambda: api.batch(reqs), ranges, "f32", reps=5, log=log)
+    log("tuned:", [(r["n_lo"], r["n_hi"], r["kc"], r["cc"]) for r in rules])
     elapsed, _, _, outs = timed(lambda: api.batch(reqs), args.steps, args.warmup, profile=False)
     total_B = sum(w.B for w in tests)
     value = total_B * args.steps / elapsed
@@ -426,15 +430,16 @@ def run_batched(args):
     stage.update(live_ms)
     shape = [(w.nx, w.ny, w.p, w.B) for w in tests]
     roof, gram_tf, res_tf = roofline(stage, shape, "f32", "ed_f32_batch256_B2000")
-    # the same tests one by one (plain path)
-    seq_steps = max(1, args.steps // 4)
-
-    def seq():
-        return [api.run(keep[2 * i], keep[2 * i + 1], w.B, w.perm_seed, "ed", w.prec,
-                        with_perm_stats=False) for i, w in enumerate(tests)]
-    e_seq, _, _, seq_out = timed(seq, seq_steps, 1, profile=False)
+    # ... and the same tests one by one again, under the batch's rules: the results must be
+    # the batch's
+    t_id = time.perf_counter()
+    seq_out = seq()
+    import torch
+    torch.cuda.synchronize()
+    log("one by one under the batch's rules: %.1f ms" % (1e3 * (time.perf_counter() - t_id)))
     same = all(a["count_ge"] == b["count_ge"] and a["statistic"] == b["statistic"]
                for a, b in zip(outs, seq_out))
+    autotune.clear()
     line = base_line(args, "ed_f32_batch256_B2000", value, elapsed, args.steps, "f32",
                      {"tests": len(tests), "B": 2000, "nx_ny_range": [50, 1500],
                       "p": [20, 100, 500], "precision": "f32",

@@ -1,7 +1,10 @@
 """Autotuner for the work shapes of the Gram and resampling stages.
 
 For each bucket of pooled sample sizes n = nx + ny the tuner times, with HIP events inside
-the library, a representative test under every candidate shape and keeps the fastest:
+the library, a representative test under every candidate shape and keeps the fastest
+(tune), or times the whole batch the rules will serve (tune_batch: in a batch the tests
+fill the chip together, so shapes that spread one small test over many workgroups lose to
+longer row units):
   resampling: kc column tiles of 128 items and cc chunks of 256 splits per workgroup
               (etest_tune_set);
   Gram:       one 128 x 128 block tile or one 256 x 256 super tile per workgroup
@@ -112,4 +115,48 @@ def tune_gram(buckets, reps=3, log=None, keep=()):
                       "gram_shape": best[1], "ms": best[0]})
     check(L.etest_tune_clear())
     install(list(keep) + rules)
+    return rules
+
+
+def tune_batch(run_batch, ranges, prec="f32", reps=5, log=None):
+    """Resampling shapes tuned on the batch they serve.  run_batch(): one synchronous pass of
+    the batch (e.g. lambda: api.batch(reqs)); ranges: the buckets [(n_lo, n_hi), ...].
+    First one shape for every bucket, then each bucket in turn with the others fixed
+    (coordinate descent), every candidate timed on the whole batch.  Returns the chosen
+    rules (and installs them)."""
+    import time
+
+    import torch
+    cands = F64_CANDIDATES if prec == "f64" else MFMA_CANDIDATES
+
+    def rules_of(shapes):
+        return [{"prec": prec, "n_lo": lo, "n_hi": hi, "kc": kc, "cc": cc}
+                for (lo, hi), (kc, cc) in zip(ranges, shapes)]
+
+    def timed(shapes):
+        install(rules_of(shapes))
+        run_batch()  # warm-up (captures the batch's graph under these rules)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            run_batch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        if log:
+            log("tune batch %s: %.4f ms" % (shapes, ms))
+        return ms
+
+    best_ms, best = min((timed([c] * len(ranges)), [c] * len(ranges)) for c in cands)
+    for i in range(len(ranges)):
+        for c in cands:
+            if c == best[i]:
+                continue
+            trial = best[:i] + [c] + best[i + 1:]
+            ms = timed(trial)
+            if ms < best_ms:
+                best_ms, best = ms, trial
+    rules = rules_of(best)
+    install(rules)
+    for r in rules:
+        r["ms"] = best_ms
     return rules

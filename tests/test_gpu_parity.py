@@ -539,6 +539,39 @@ def test_autotuner_picks_a_shape_and_results_hold():
     compare_run(g, o, "f32", "autotuned")
 
 
+def test_batch_tuner_picks_shapes_and_results_hold():
+    """The batch tuner times candidate shapes on the whole batch, per size bucket, and
+    installs the fastest; under those rules the batch equals its tests run alone, and a test
+    of it matches the oracle."""
+    from paper_2406_06488_amd import autotune
+    specs = [(300, 250, 20, 600), (90, 60, 100, 600), (700, 650, 40, 1000), (40, 50, 7, 300)]
+    data, reqs, keep = [], [], []
+    for t, (nx, ny, p, B) in enumerate(specs):
+        X, Y = _data(nx, ny, p, 140 + t, "f32")
+        Xd, Yd = _dev(X, "f32"), _dev(Y, "f32")
+        data.append((X, Y))
+        keep += [Xd, Yd]
+        reqs.append(api.make_request(Xd, Yd, B, 160 + t, "ed", "f32"))
+    reqs = (api.Request * len(reqs))(*reqs)
+    ranges = [(0, 1024), (1024, 1 << 31)]
+    try:
+        rules = autotune.tune_batch(lambda: api.batch(reqs), ranges, "f32", reps=1, log=say)
+        assert [(r["n_lo"], r["n_hi"]) for r in rules] == ranges
+        assert all((r["kc"], r["cc"]) in autotune.MFMA_CANDIDATES for r in rules)
+        outs = api.batch(reqs)
+        alone = [api.run(keep[2 * t], keep[2 * t + 1], B, 160 + t, "ed", "f32")
+                 for t, (_, _, _, B) in enumerate(specs)]
+        torch.cuda.synchronize()
+    finally:
+        autotune.clear()
+    for t in range(len(specs)):
+        for k in ("statistic", "threshold", "count_ge", "p_value"):
+            assert outs[t][k] == alone[t][k], (t, k)
+    X, Y = data[2]
+    o = oracle.run_test(X.astype(np.float64), Y.astype(np.float64), specs[2][3], 162)
+    compare_run(alone[2], o, "f32", "batch-tuned")
+
+
 # --------------------------------------------------------------------------- Gram shapes
 
 def _with_gram_shape(shape, prec, n, fn):
